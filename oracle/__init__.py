@@ -1,0 +1,161 @@
+"""CPU oracle for the XCSR multigraph transpose -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. It wraps ``oracle.c`` (a plain single-threaded
+counting-sort transpose written from the paper's definitions) and adds two
+pure-Python/numpy cross-checks: ``brute`` (sort every cell by its transposed
+key) and ``staged`` (a rank-by-rank simulation of the paper's staged
+algorithm). The GPU library shares no code with anything here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -5
+FAULT_NONE, FAULT_UNSTABLE, FAULT_SHORT_COPY, FAULT_INDEX_FOR_ROW, FAULT_SWAP_XFER, \
+    FAULT_INCLUSIVE_ROWPTR = range(6)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle (plain C, gcc) in place."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", _SRC,
+                               "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        lib.mgo_set_fault.argtypes = [ctypes.c_int]
+        lib.mgo_validate.argtypes = [i64, i64, i32, vp, vp, vp, i32, vp]
+        lib.mgo_transpose.argtypes = [i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.mgo_partition_counts.argtypes = [i64, i64, i32, vp, vp, vp, i32, vp, vp, vp, vp,
+                                             vp, vp, vp]
+        lib.mgo_transpose_columns.argtypes = [i64, i64, i32, vp, vp, vp, vp, i64, i64, vp, vp,
+                                              vp, vp, vp, vp, vp]
+        for f in (lib.mgo_validate, lib.mgo_transpose, lib.mgo_partition_counts,
+                  lib.mgo_transpose_columns):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data if a.size else None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int):
+        super().__init__(f"oracle rejected the input (status {code})")
+        self.code = code
+
+
+@dataclass
+class Transposed:
+    """Transposed XCSR: t_row_ptr has n_cols+1 entries; t_col holds original row ids."""
+    t_row_ptr: np.ndarray
+    t_col: np.ndarray
+    t_payload_off: np.ndarray
+    t_payload: np.ndarray
+    perm: np.ndarray
+
+
+@dataclass
+class PartitionCounts:
+    xfer_cells: np.ndarray   # [R, R], [src, dst]
+    xfer_bytes: np.ndarray   # [R, R]
+    part_cell_off: np.ndarray  # [R+1]
+    part_byte_off: np.ndarray  # [R+1]
+    sdispls: np.ndarray      # [R, R]: send displacement of block src->dst inside src's send buffer
+    rdispls: np.ndarray      # [R, R]: [dst, src] receive displacement inside dst's receive buffer
+
+
+def set_fault(code: int) -> None:
+    """Plant one specific mistake in the oracle (tests of the pins only)."""
+    _load().mgo_set_fault(int(code))
+
+
+def validate(a, n_parts: int = 0) -> int:
+    b = np.ascontiguousarray(a.bounds, dtype=np.int64) if n_parts else None
+    return _load().mgo_validate(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col),
+                                _p(a.payload_off), n_parts, _p(b))
+
+
+def transpose(a) -> Transposed:
+    """Transpose of a workloads.Csr (plain definition, Gustavson counting sort)."""
+    dt = np.int32 if a.offset_width == 4 else np.int64
+    nnz = a.nnz
+    t_row_ptr = np.zeros(a.n_cols + 1, dtype=dt)
+    t_col = np.zeros(nnz, dtype=np.int32)
+    t_poff = np.zeros(nnz + 1, dtype=dt)
+    t_payload = np.zeros(a.payload_bytes, dtype=np.uint8)
+    perm = np.zeros(nnz, dtype=np.uint32)
+    st = _load().mgo_transpose(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col),
+                               _p(a.payload_off), _p(a.payload), _p(t_row_ptr), _p(t_col),
+                               _p(t_poff), _p(t_payload), _p(perm))
+    if st != OK:
+        raise OracleError(st)
+    return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)
+
+
+def partition_counts(a) -> PartitionCounts:
+    R = a.n_parts
+    bounds = np.ascontiguousarray(a.bounds, dtype=np.int64)
+    x = np.zeros((R, R), dtype=np.int64)
+    b = np.zeros((R, R), dtype=np.int64)
+    pc = np.zeros(R + 1, dtype=np.int64)
+    pb = np.zeros(R + 1, dtype=np.int64)
+    sd = np.zeros((R, R), dtype=np.int64)
+    rd = np.zeros((R, R), dtype=np.int64)
+    st = _load().mgo_partition_counts(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr),
+                                      _p(a.col), _p(a.payload_off), R, _p(bounds), _p(x), _p(b),
+                                      _p(pc), _p(pb), _p(sd), _p(rd))
+    if st != OK:
+        raise OracleError(st)
+    return PartitionCounts(x, b, pc, pb, sd, rd)
+
+
+def transpose_columns(a, c_lo: int, c_hi: int) -> Transposed:
+    """Transpose restricted to output rows [c_lo, c_hi); offsets relative to the slice."""
+    lib = _load()
+    cells = ctypes.c_int64(0)
+    nbytes = ctypes.c_int64(0)
+    args = (a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col), _p(a.payload_off),
+            _p(a.payload), c_lo, c_hi)
+    st = lib.mgo_transpose_columns(*args, None, None, None, None, None, ctypes.byref(cells),
+                                   ctypes.byref(nbytes))
+    if st != OK:
+        raise OracleError(st)
+    t_row_ptr = np.zeros(c_hi - c_lo + 1, dtype=np.int64)
+    t_col = np.zeros(cells.value, dtype=np.int32)
+    t_poff = np.zeros(cells.value + 1, dtype=np.int64)
+    t_payload = np.zeros(nbytes.value, dtype=np.uint8)
+    perm = np.zeros(cells.value, dtype=np.uint32)
+    st = lib.mgo_transpose_columns(*args, _p(t_row_ptr), _p(t_col), _p(t_poff[:-1]) if cells.value else None,
+                                   _p(t_payload), _p(perm), None, None)
+    if st != OK:
+        raise OracleError(st)
+    t_poff[-1] = nbytes.value
+    return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)

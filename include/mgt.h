@@ -1,0 +1,206 @@
+/*
+ * mgt -- transpose of row-distributed XCSR multigraphs on one MI355X (gfx950).
+ *
+ * C ABI of libmgt.so. Plain pointers and sizes only; every device buffer is
+ * owned by the caller. All launches are asynchronous on the caller's stream.
+ *
+ * Terms (Magalhaes & Schurmann, arXiv 2012.06012):
+ *  - XCSR (Section 2): CSR (row offsets row_ptr, column ids col) plus a value
+ *    list per cell. Here a cell's value list is an opaque byte string:
+ *    payload[payload_off[k] .. payload_off[k+1]) belongs to cell k. Cells may
+ *    repeat a (row, col) pair: a multigraph keeps each edge as its own cell.
+ *  - Transpose (Section 2): M^T_ij = M_ji; edge {i, j, e} becomes {j, i, e}.
+ *    Output row j lists the input cells whose column is j, ordered by input row
+ *    and, for repeated (row, col) cells, in their original order; each cell's
+ *    payload moves with it. t_col holds the original row ids. Rows of the
+ *    output are therefore always sorted by column; if the input's rows are
+ *    sorted by column, transposing twice returns the input exactly (the
+ *    paper's involution, Section 3).
+ *  - Partitions (ranks, Section 2 step 1; Section 3 row intervals): partition r
+ *    owns rows [part_bounds[r], part_bounds[r+1]) with 0-based r. A partitioned
+ *    matrix is square and the output's rows (= input columns) are split by the
+ *    same bounds. xfer_cells[r*R+s] counts the cells partition r sends to
+ *    partition s (the owner of their column; Section 2 step 2), xfer_bytes the
+ *    matching payload bytes (Section 3, value counts per recipient, Fig. 6).
+ *
+ * Sizes and limits: n_rows, n_cols < 2^31 (col ids are int32); nnz < 2^32;
+ * payload offsets are 4- or 8-byte signed integers (offset_width), as are
+ * row_ptr and the transposed offsets. A single cell's payload must be < 2^32
+ * bytes, and any 16,384 consecutive cells must carry < 2^32 payload bytes
+ * (checked on the device on every call: *d_status = MGT_EUNSUPPORTED).
+ *
+ * Errors: functions return an mgt_status. Host-detectable errors (bad
+ * descriptor, NULL pointer, workspace too small, unsupported sizes) are
+ * returned before anything is launched and leave the outputs untouched.
+ * With MGT_VALIDATE, the device also checks the data (row_ptr and payload_off
+ * start at 0, never decrease and end at nnz / payload_bytes; every col lies in
+ * [0, n_cols)) and writes MGT_ERANGE to *d_status if it does not hold; the
+ * remaining stages then skip their work and the outputs are undefined. Without
+ * MGT_VALIDATE, invalid data is undefined behaviour. On success *d_status is
+ * MGT_OK. d_status may be NULL.
+ *
+ * Thread safety: a plan is immutable after creation and may be used from
+ * several threads; concurrent calls need distinct workspaces (and, for the
+ * batch entry point, distinct plans, since a plan owns its staging buffer).
+ */
+#ifndef MGT_H
+#define MGT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGT_OK = 0,
+  MGT_EINVAL = -1,       /* bad descriptor, pointer, bounds or argument          */
+  MGT_ERANGE = -2,       /* data out of range (device-side check, MGT_VALIDATE)  */
+  MGT_ENOMEM = -3,       /* workspace too small / host allocation failed         */
+  MGT_EHIP = -4,         /* a HIP runtime call failed                            */
+  MGT_EUNSUPPORTED = -5, /* sizes beyond the documented limits                   */
+  MGT_ECANCELED = -6     /* batch item skipped because another item failed       */
+} mgt_status;
+
+enum {
+  MGT_VALIDATE = 1u << 0,     /* device-side data checks, result in *d_status            */
+  MGT_EMIT_PERM = 1u << 1,    /* callers will pass perm: perm[p] = input cell of output p */
+  MGT_DEBUG_TIMING = 1u << 2  /* record per-stage times (mgt_plan_stage_times)           */
+};
+
+typedef struct mgt_plan_s* mgt_plan_t;
+
+/* Describes one matrix. For n_parts > 1 the matrix must be square. */
+typedef struct {
+  int64_t n_rows, n_cols;
+  int64_t nnz;             /* = row_ptr[n_rows]                                    */
+  int64_t payload_bytes;   /* = payload_off[nnz]                                   */
+  int32_t offset_width;    /* 4 or 8: element size of row_ptr, payload_off and the
+                              transposed offsets                                    */
+  int32_t n_parts;         /* R >= 1 partitions (R <= 1024)                         */
+  const int64_t* part_bounds; /* host, R+1 entries: 0 = b[0] <= b[1] <= ... <= b[R]
+                              = n_rows; empty partitions allowed; may be NULL when
+                              R == 1                                                */
+  uint32_t flags;          /* MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING      */
+} mgt_desc;
+
+/*
+ * Creates a plan for matrices with this descriptor (sizes and partition bounds
+ * are copied). Chooses the digit schedule and tile sizes and reports the
+ * device workspace the transpose calls need. Host only; launches nothing.
+ */
+int mgt_plan(const mgt_desc* desc, mgt_plan_t* out, size_t* workspace_bytes);
+int mgt_plan_destroy(mgt_plan_t plan);
+
+/*
+ * Plain transpose (Section 2 definition; the partition bounds of the plan, if
+ * any, are ignored). Device pointers:
+ *   inputs : row_ptr[n_rows+1], col[nnz], payload_off[nnz+1], payload[payload_bytes]
+ *   outputs: t_row_ptr[n_cols+1], t_col[nnz], t_payload_off[nnz+1],
+ *            t_payload[payload_bytes], perm[nnz] (only with MGT_EMIT_PERM, else NULL)
+ * payload / t_payload may be NULL when payload_bytes == 0. Outputs must not
+ * overlap inputs. workspace: >= the size mgt_plan reported, 256-byte aligned.
+ */
+int mgt_transpose(mgt_plan_t plan, const void* row_ptr, const int32_t* col,
+                  const void* payload_off, const uint8_t* payload, void* t_row_ptr,
+                  int32_t* t_col, void* t_payload_off, uint8_t* t_payload, uint32_t* perm,
+                  void* workspace, size_t workspace_bytes, int32_t* d_status,
+                  hipStream_t stream);
+
+/*
+ * Partitioned transpose: the paper's distributed transpose with the R ranks as
+ * logical partitions of one device (Section 3: local transpose composed with
+ * the view swap). Same inputs and outputs as mgt_transpose -- partition s of
+ * the result is the slice [part_cell_off[s], part_cell_off[s+1]) of t_col /
+ * t_payload_off (bytes [part_byte_off[s], part_byte_off[s+1]) of t_payload) and
+ * t_row_ptr[part_bounds[s] .. part_bounds[s+1]] -- plus, in device memory:
+ *   xfer_cells[R*R], xfer_bytes[R*R]  row-major [src][dst] (Section 2 step 2,
+ *                                     Section 3 value counts)
+ *   part_cell_off[R+1], part_byte_off[R+1]
+ *   sdispls[R*R]  (may be NULL) send displacement of block src->dst inside
+ *                 src's packed send order: exclusive scan of xfer_cells[src][.]
+ *   rdispls[R*R]  (may be NULL) [dst][src]: receive displacement of block
+ *                 src->dst inside partition dst: exclusive scan of
+ *                 xfer_cells[.][dst] over src (Alltoallv displacements)
+ */
+int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_t* col,
+                              const void* payload_off, const uint8_t* payload, void* t_row_ptr,
+                              int32_t* t_col, void* t_payload_off, uint8_t* t_payload,
+                              uint32_t* perm, int64_t* xfer_cells, int64_t* xfer_bytes,
+                              int64_t* part_cell_off, int64_t* part_byte_off, int64_t* sdispls,
+                              int64_t* rdispls, void* workspace, size_t workspace_bytes,
+                              int32_t* d_status, hipStream_t stream);
+
+/* ------------------------------------------------------------------ batches */
+
+/* Capacity of a batch plan. Every submitted batch must fit all limits. */
+typedef struct {
+  int32_t max_items;
+  int32_t offset_width;     /* shared by all items (4 or 8)                        */
+  int64_t max_total_nnz;    /* sum of nnz over a batch                             */
+  int64_t max_total_cols;   /* sum of n_cols                                       */
+  int64_t max_total_rows;   /* sum of n_rows                                       */
+  int64_t max_total_parts;  /* sum of n_parts                                      */
+  int64_t max_item_nnz;     /* largest single item                                 */
+  int64_t max_item_cols;
+  uint32_t flags;           /* MGT_VALIDATE | MGT_EMIT_PERM                       */
+} mgt_batch_limits;
+
+/* One matrix of a batch: its descriptor (n_parts >= 1; partitioned outputs
+ * are written when n_parts > 1) and its device buffers. */
+typedef struct {
+  mgt_desc desc;
+  const void* row_ptr;
+  const int32_t* col;
+  const void* payload_off;
+  const uint8_t* payload;
+  void* t_row_ptr;
+  int32_t* t_col;
+  void* t_payload_off;
+  uint8_t* t_payload;
+  uint32_t* perm;           /* NULL unless MGT_EMIT_PERM                            */
+  int64_t* xfer_cells;      /* n_parts > 1 only; else NULL                          */
+  int64_t* xfer_bytes;
+  int64_t* part_cell_off;
+  int64_t* part_byte_off;
+} mgt_item;
+
+/* Creates a batch plan. *workspace_bytes receives an estimate for a batch at
+ * the limits (payload bytes excluded); mgt_batch_workspace gives the exact
+ * requirement of a particular batch. */
+int mgt_batch_plan(const mgt_batch_limits* limits, mgt_plan_t* out, size_t* workspace_bytes);
+
+/* Exact device workspace that mgt_batch_submit needs for these items. Host only. */
+int mgt_batch_workspace(mgt_plan_t batch_plan, const mgt_item* items, int32_t n_items,
+                        size_t* workspace_bytes);
+
+/*
+ * Transposes every item of the batch with one fixed sequence of stage kernels
+ * whose grids cover all items at once (the item count does not change the
+ * number of launches). Items may differ in size, payload width and partition
+ * count. The descriptor table is copied to the device through the plan's
+ * pinned staging buffer; the call returns once the copy is queued. d_status
+ * (may be NULL) receives one status word per item. If `done` is not NULL it
+ * is recorded on `stream` after the last stage.
+ */
+int mgt_batch_submit(mgt_plan_t batch_plan, const mgt_item* items, int32_t n_items,
+                     void* workspace, size_t workspace_bytes, int32_t* d_status,
+                     hipStream_t stream, hipEvent_t done);
+
+/* ------------------------------------------------------------------ utilities */
+
+/* Per-stage device times of the last call made with MGT_DEBUG_TIMING
+ * (synchronises on the plan's events). names may be NULL. */
+int mgt_plan_stage_times(mgt_plan_t plan, float* ms, const char** names, int32_t capacity,
+                         int32_t* count);
+
+/* Library version string. */
+const char* mgt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGT_H */

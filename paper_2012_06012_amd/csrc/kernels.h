@@ -1,0 +1,94 @@
+// Host-side launchers of the transpose stages (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mgt_internal.h"
+
+namespace mgt {
+
+// Geometry shared by host and device.
+constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
+constexpr int kSub = 1024;          // cells sorted in LDS at once
+constexpr int kScanBlock = 4096;    // elements per scan workgroup
+
+// Arguments of a partition pass (hist and scatter share them).
+struct PassArgs {
+  const ItemDev* items;
+  const Seg* segs;
+  uint32_t nseg;
+  uint32_t pass;
+  const uint64_t* tstart;     // nseg + 1
+  const uint64_t* hstart;     // nseg + 1
+  const uint2* ks_in;         // (key, size) records, pass >= 2
+  const uint2* rk_in;         // (row, index) records, pass >= 2
+  const uint8_t* pay_in;      // payload bytes, pass >= 2
+  uint2* ks_out;
+  uint2* rk_out;
+  uint8_t* pay_out;
+  uint32_t* hcnt;             // [entry] cells of (segment, digit, tile)
+  uint32_t* hbyt;             // [entry] payload bytes of (segment, digit, tile)
+  uint32_t* ttot;             // [tile] payload bytes of the tile
+  const uint64_t* ocnt;       // exclusive scan of hcnt (n + 1)
+  const uint64_t* obyt;       // exclusive scan of hbyt (n + 1)
+  const uint64_t* tsrc;       // exclusive scan of ttot (tiles + 1)
+  int32_t* item_status;
+  int32_t* abort_flag;
+  uint64_t g8;                // grid size (multiple of 8)
+  uint32_t tile_cells;        // multiple of kSub
+  int32_t offset_width;
+};
+
+struct ChildArgs {
+  const ItemDev* items;
+  const Seg* segs;            // parents
+  uint32_t nseg;
+  uint32_t pass;              // pass whose output the children describe (0-based)
+  const uint64_t* tstart;
+  const uint64_t* hstart;
+  const uint64_t* ocnt;
+  const uint64_t* obyt;
+  Seg* children;
+  uint32_t* child_tiles;
+  uint32_t* child_hsize;
+  uint32_t tile_cells;
+  const int32_t* abort_flag;
+};
+
+struct FinishArgs {
+  const ItemDev* items;
+  const Seg* buckets;
+  uint32_t nbuckets;
+  const uint2* ks_in;
+  const uint2* rk_in;
+  const uint8_t* pay_in;
+  const int32_t* abort_flag;
+  int32_t offset_width;
+};
+
+hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,
+                       uint32_t* hsize0, int32_t* item_status, int32_t* abort_flag,
+                       uint32_t tile_cells, hipStream_t s);
+hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
+                           int32_t* item_status, int32_t* abort_flag, int32_t offset_width,
+                           hipStream_t s);
+// Exclusive scans of `narr` (1 or 2) u32 arrays of length *n (<= n_max) into
+// u64 outputs of length n + 1 (out[n] = total).
+hipError_t launch_scan(const uint32_t* in0, uint64_t* out0, const uint32_t* in1, uint64_t* out1,
+                       const uint64_t* n_dev, uint64_t n_max, uint64_t* block_sums,
+                       hipStream_t s);
+hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
+hipError_t launch_children(const ChildArgs& a, hipStream_t s);
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* abort_flag,
+                        int32_t offset_width, hipStream_t s);
+hipError_t launch_status_out(const int32_t* item_status, const int32_t* abort_flag,
+                             uint32_t n_items, int32_t* d_status, hipStream_t s);
+
+// Scratch needed by launch_scan for n_max elements (bytes).
+inline uint64_t scan_scratch_bytes(uint64_t n_max) {
+  return 2 * 8 * ((n_max + kScanBlock - 1) / kScanBlock + 1) + 64;
+}
+
+}  // namespace mgt

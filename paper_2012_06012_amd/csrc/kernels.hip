@@ -1,0 +1,898 @@
+// Device stages of the XCSR multigraph transpose (gfx950).
+//
+// The transpose is a stable sort of the cells by column (Section 2 definition,
+// M^T_ij = M_ji, with repeated cells kept in input order), carrying each cell's
+// row id, index and payload bytes. It is done as a few stable partition passes
+// over the column bits (most significant first) followed by a per-bucket
+// counting sort in LDS; see mgt_internal.h for the data flow.
+#include <hip/hip_runtime.h>
+
+#include "../../include/mgt.h"
+#include "kernels.h"
+#include "prims.h"
+
+namespace mgt {
+
+constexpr int kNW = kBlock / kWave;        // waves per workgroup
+constexpr int kItems = kSub / kBlock;      // cells per lane per sub-chunk
+constexpr int kWaveCells = kSub / kNW;     // cells of one wave per sub-chunk
+constexpr int kFinishCols = 1 << kMaxFinishBits;
+static_assert(kItems * kWave * kNW == kSub, "sub-chunk geometry");
+
+// ----------------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int64_t ld_off(const void* p, uint64_t i, int ow) {
+  return ow == 4 ? (int64_t)((const int32_t*)p)[i] : ((const int64_t*)p)[i];
+}
+__device__ __forceinline__ void st_off(void* p, uint64_t i, int64_t v, int ow) {
+  if (ow == 4) ((int32_t*)p)[i] = (int32_t)v;
+  else ((int64_t*)p)[i] = v;
+}
+
+__device__ __forceinline__ int ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
+
+__device__ __forceinline__ uint32_t seg_fanout(const Seg& s, uint32_t R) {
+  return s.mode ? (R << s.bits) : (1u << s.bits);
+}
+
+// Largest s with tstart[s] <= t (the segment that owns tile t).
+__device__ __forceinline__ uint32_t find_seg(const uint64_t* tstart, uint32_t nseg, uint64_t t) {
+  uint32_t lo = 0, hi = nseg;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (tstart[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Row owning cell k: the largest r in [lo, hi] with row_ptr[r] <= k.
+__device__ __forceinline__ uint32_t row_of(const void* rp, int ow, uint64_t k, uint32_t lo,
+                                           uint32_t hi) {
+  uint32_t a = lo, b = hi + 1;
+  while (b - a > 1) {
+    const uint32_t mid = (a + b) >> 1;
+    if ((uint64_t)ld_off(rp, mid, ow) <= k) a = mid;
+    else b = mid;
+  }
+  return a;
+}
+
+// Partition owning vertex v: largest p with bounds[p] <= v (0-based ranks).
+__device__ __forceinline__ uint32_t owner_of(const int64_t* lb, uint32_t R, int64_t v) {
+  uint32_t lo = 0, hi = R;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (lb[mid] <= v) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Digit of a column inside a segment. Bits mode: the next `bits` bits of
+// (key - key_lo) below `shift`. Partition mode (pass 1 of a partitioned
+// matrix): the destination partition, then the top `bits` bits of the column
+// inside it. Out-of-range keys (invalid input) are clamped into the fan-out.
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, const Seg& s, const int64_t* lb,
+                                             uint32_t R) {
+  const uint32_t m = (1u << s.bits) - 1u;
+  if (s.mode == 0) {
+    const uint32_t d = (key - s.key_lo) >> s.shift;
+    return d > m ? m : d;
+  }
+  const uint32_t p = owner_of(lb, R, (int64_t)key);
+  const int64_t rel = (int64_t)key - lb[p];
+  uint32_t sub = rel < 0 ? 0u : (uint32_t)(rel >> s.shift);
+  sub = sub > m ? m : sub;
+  return (p << s.bits) | sub;
+}
+
+__device__ __forceinline__ void raise_status(int32_t* item_status, int32_t* abort_flag, int idx,
+                                             int32_t code) {
+  item_status[idx] = code;
+  __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool aborted(const int32_t* abort_flag) {
+  return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// ----------------------------------------------------------------------------- init / validate
+
+__global__ __launch_bounds__(kBlock) void k_init(const ItemDev* items, uint32_t n_items,
+                                                 Seg* segs0, uint32_t* tiles0, uint32_t* hsize0,
+                                                 int32_t* item_status, int32_t* abort_flag,
+                                                 uint32_t tile_cells) {
+  const uint32_t i = blockIdx.x;
+  if (i >= n_items) return;
+  const ItemDev& it = items[i];
+  if (threadIdx.x == 0) {
+    Seg s;
+    s.cell0 = it.cell_base;
+    s.byte0 = it.byte_base;
+    s.len = (uint32_t)it.nnz;
+    s.key_lo = 0;
+    s.key_hi = (uint32_t)it.n_cols;
+    s.item = i;
+    s.bits = (uint32_t)it.bits[0];
+    s.shift = (uint32_t)(it.key_bits - it.bits[0]);
+    s.mode = (uint32_t)it.part_mode;
+    s.pad = 0;
+    segs0[i] = s;
+    const uint32_t tiles = (uint32_t)((it.nnz + tile_cells - 1) / tile_cells);
+    const uint32_t F = it.part_mode ? ((uint32_t)it.n_parts << it.bits[0]) : (1u << it.bits[0]);
+    tiles0[i] = tiles;
+    hsize0[i] = tiles * F;
+    item_status[it.status_index] = MGT_OK;
+    if (i == 0) *abort_flag = 0;
+  }
+  if (it.part_mode && it.xfer_cells) {
+    const uint64_t rr = (uint64_t)it.n_parts * (uint64_t)it.n_parts;
+    for (uint64_t e = threadIdx.x; e < rr; e += kBlock) {
+      it.xfer_cells[e] = 0;
+      it.xfer_bytes[e] = 0;
+    }
+  }
+}
+
+// Device-side data checks (MGT_VALIDATE): offsets start at 0, never decrease
+// and end at nnz / payload_bytes; every column id lies in [0, n_cols); every
+// cell's payload is smaller than 2^32 bytes.
+__global__ __launch_bounds__(kBlock) void k_validate(const ItemDev* items, int32_t* item_status,
+                                                     int32_t* abort_flag, int ow) {
+  const ItemDev& it = items[blockIdx.y];
+  const uint64_t n_rows = (uint64_t)it.n_rows, nnz = (uint64_t)it.nnz;
+  const uint64_t span = (n_rows > nnz ? n_rows : nnz) + 1;
+  bool bad = false;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < span;
+       i += (uint64_t)gridDim.x * kBlock) {
+    if (i <= n_rows) {
+      const int64_t r0 = ld_off(it.row_ptr, i, ow);
+      if (i == 0 && r0 != 0) bad = true;
+      if (i < n_rows && ld_off(it.row_ptr, i + 1, ow) < r0) bad = true;
+      if (i == n_rows && r0 != it.nnz) bad = true;
+    }
+    if (i <= nnz) {
+      const int64_t p0 = ld_off(it.poff, i, ow);
+      if (i == 0 && p0 != 0) bad = true;
+      if (i == nnz && p0 != it.payload_bytes) bad = true;
+      if (i < nnz) {
+        const int64_t d = ld_off(it.poff, i + 1, ow) - p0;
+        if (d < 0 || d >= ((int64_t)1 << 32)) bad = true;
+        const int32_t c = it.col[i];
+        if (c < 0 || (int64_t)c >= it.n_cols) bad = true;
+      }
+    }
+  }
+  if (bad) raise_status(item_status, abort_flag, it.status_index, MGT_ERANGE);
+}
+
+// ----------------------------------------------------------------------------- scans
+
+// Exclusive scans (u32 in, u64 out, out[n] = total) by reduce / spine / down-sweep.
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* in0, const uint32_t* in1,
+                                                        const uint64_t* n_dev, uint64_t n_max,
+                                                        uint64_t* bsum, uint64_t nb_cap) {
+  __shared__ uint64_t red[kNW + 1];
+  const uint64_t n = n_dev ? min(*n_dev, n_max) : n_max;
+  const uint64_t lo = (uint64_t)blockIdx.x * kScanBlock;
+  if (lo >= n) return;
+  const uint64_t hi = min(n, lo + kScanBlock);
+  uint64_t s0 = 0, s1 = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+    s0 += in0[i];
+    if (in1) s1 += in1[i];
+  }
+  uint64_t t0, t1;
+  block_excl_scan<kNW>(s0, red, t0);
+  block_excl_scan<kNW>(s1, red, t1);
+  if (threadIdx.x == 0) {
+    bsum[blockIdx.x] = t0;
+    bsum[nb_cap + blockIdx.x] = t1;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_spine(const uint64_t* n_dev, uint64_t n_max,
+                                                     uint64_t* bsum, uint64_t nb_cap,
+                                                     uint64_t* out0, uint64_t* out1) {
+  __shared__ uint64_t red[1024 / kWave + 1];
+  const uint64_t n = n_dev ? min(*n_dev, n_max) : n_max;
+  const uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  for (int arr = 0; arr < (out1 ? 2 : 1); ++arr) {
+    uint64_t* b = bsum + (uint64_t)arr * nb_cap;
+    uint64_t carry = 0;
+    for (uint64_t base = 0; base < nb; base += 1024) {
+      const uint64_t i = base + threadIdx.x;
+      const uint64_t v = i < nb ? b[i] : 0;
+      uint64_t tot;
+      const uint64_t ex = block_excl_scan<1024 / kWave>(v, red, tot);
+      if (i < nb) b[i] = carry + ex;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) (arr == 0 ? out0 : out1)[n] = carry;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in0, uint64_t* out0,
+                                                      const uint32_t* in1, uint64_t* out1,
+                                                      const uint64_t* n_dev, uint64_t n_max,
+                                                      const uint64_t* bsum, uint64_t nb_cap) {
+  __shared__ uint64_t red[kNW + 1];
+  constexpr int kPer = kScanBlock / kBlock;
+  const uint64_t n = n_dev ? min(*n_dev, n_max) : n_max;
+  const uint64_t lo = (uint64_t)blockIdx.x * kScanBlock;
+  if (lo >= n) return;
+  for (int arr = 0; arr < (in1 ? 2 : 1); ++arr) {
+    const uint32_t* in = arr ? in1 : in0;
+    uint64_t* out = arr ? out1 : out0;
+    const uint64_t base = bsum[(uint64_t)arr * nb_cap + blockIdx.x];
+    const uint64_t t0 = lo + (uint64_t)threadIdx.x * kPer;
+    uint32_t v[kPer];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      v[j] = (t0 + j < n) ? in[t0 + j] : 0u;
+      s += v[j];
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan<kNW>(s, red, tot) + base;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      if (t0 + j < n) out[t0 + j] = ex;
+      ex += v[j];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- pass: histogram
+
+__global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
+  __shared__ uint32_t s_cnt[kMaxFanout];
+  __shared__ uint32_t s_byt[kMaxFanout];
+  __shared__ int64_t s_lb[kMaxParts + 1];
+  __shared__ Seg s_seg;
+  __shared__ uint32_t s_si;
+  __shared__ uint64_t s_red[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
+  if (tile >= a.tstart[a.nseg]) return;
+  if (threadIdx.x == 0) {
+    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
+    s_si = si;
+    s_seg = a.segs[si];
+  }
+  __syncthreads();
+  const Seg sg = s_seg;
+  const uint32_t si = s_si;
+  const ItemDev* it = &a.items[sg.item];
+  const uint32_t R = (uint32_t)it->n_parts;
+  const uint32_t F = seg_fanout(sg, R);
+  if (sg.mode)
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = it->bounds[i];
+  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+    s_cnt[d] = 0;
+    s_byt[d] = 0;
+  }
+  __syncthreads();
+  const uint64_t j = tile - a.tstart[si];
+  const uint64_t c_begin = j * a.tile_cells;
+  const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
+  const int ow = a.offset_width;
+  uint64_t mybytes = 0;
+  if (a.pass == 0) {
+    const uint64_t kbase = sg.cell0 - it->cell_base;
+    const int32_t* col = it->col;
+    const void* poff = it->poff;
+    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kBlock) {
+      const uint64_t k = kbase + c;
+      const uint32_t key = (uint32_t)col[k];
+      const uint32_t sz = (uint32_t)(ld_off(poff, k + 1, ow) - ld_off(poff, k, ow));
+      const uint32_t d = digit_of(key, sg, s_lb, R);
+      atomicAdd(&s_cnt[d], 1u);
+      atomicAdd(&s_byt[d], sz);
+      mybytes += sz;
+    }
+  } else {
+    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kBlock) {
+      const uint2 ks = a.ks_in[sg.cell0 + c];
+      const uint32_t d = digit_of(ks.x, sg, s_lb, R);
+      atomicAdd(&s_cnt[d], 1u);
+      atomicAdd(&s_byt[d], ks.y);
+      mybytes += ks.y;
+    }
+  }
+  uint64_t tot;
+  block_excl_scan<kNW>(mybytes, s_red, tot);  // also orders the LDS histogram updates
+  const uint64_t nt = a.tstart[si + 1] - a.tstart[si];
+  const uint64_t hb = a.hstart[si];
+  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+    a.hcnt[hb + (uint64_t)d * nt + j] = s_cnt[d];
+    a.hbyt[hb + (uint64_t)d * nt + j] = s_byt[d];
+  }
+  if (threadIdx.x == 0) {
+    a.ttot[tile] = (uint32_t)tot;
+    if (tot >> 32) raise_status(a.item_status, a.abort_flag, it->status_index, MGT_EUNSUPPORTED);
+  }
+}
+
+// ----------------------------------------------------------------------------- children
+
+__global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
+  if (aborted(a.abort_flag)) return;
+  const uint32_t si = blockIdx.x;
+  const Seg sg = a.segs[si];
+  const ItemDev* it = &a.items[sg.item];
+  const uint32_t R = (uint32_t)it->n_parts;
+  const uint32_t F = seg_fanout(sg, R);
+  const uint64_t nt = a.tstart[si + 1] - a.tstart[si];
+  const uint64_t hb = a.hstart[si];
+  const uint32_t next = a.pass + 1;
+  const uint32_t nbits = next < (uint32_t)it->n_levels ? (uint32_t)it->bits[next] : 0u;
+  const uint64_t cbase = it->seg_base[next] + (uint64_t)(si - it->seg_base[a.pass]) * F;
+  const uint32_t rb = sg.shift;  // bits spanned by one child's column range
+  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+    uint64_t c0, c1, b0, b1;
+    if (nt) {
+      c0 = a.ocnt[hb + (uint64_t)d * nt];
+      c1 = a.ocnt[hb + (uint64_t)(d + 1) * nt];
+      b0 = a.obyt[hb + (uint64_t)d * nt];
+      b1 = a.obyt[hb + (uint64_t)(d + 1) * nt];
+    } else {
+      c0 = c1 = sg.cell0;
+      b0 = b1 = sg.byte0;
+    }
+    uint64_t lo, hi;
+    if (sg.mode == 0) {
+      lo = (uint64_t)sg.key_lo + ((uint64_t)d << sg.shift);
+      hi = lo + (1ull << sg.shift);
+      lo = lo < sg.key_hi ? lo : sg.key_hi;
+      hi = hi < sg.key_hi ? hi : sg.key_hi;
+    } else {
+      const uint32_t p = d >> sg.bits, jj = d & ((1u << sg.bits) - 1u);
+      const uint64_t blo = (uint64_t)it->bounds[p], bhi = (uint64_t)it->bounds[p + 1];
+      lo = blo + ((uint64_t)jj << sg.shift);
+      hi = lo + (1ull << sg.shift);
+      lo = lo < bhi ? lo : bhi;
+      hi = hi < bhi ? hi : bhi;
+    }
+    Seg ch;
+    ch.cell0 = c0;
+    ch.byte0 = b0;
+    ch.len = (uint32_t)(c1 - c0);
+    ch.key_lo = (uint32_t)lo;
+    ch.key_hi = (uint32_t)hi;
+    ch.item = sg.item;
+    ch.bits = nbits;
+    ch.shift = rb >= nbits ? rb - nbits : 0u;
+    ch.mode = 0;
+    ch.pad = 0;
+    (void)b1;
+    a.children[cbase + d] = ch;
+    if (a.child_tiles) {
+      const uint32_t tiles = (uint32_t)((ch.len + a.tile_cells - 1) / a.tile_cells);
+      a.child_tiles[cbase + d] = tiles;
+      a.child_hsize[cbase + d] = tiles << nbits;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------- shared sub-chunk sort
+
+// LDS state of one stable sub-chunk sort.
+struct SortLds {
+  uint32_t key[kSub];
+  uint32_t sz[kSub];
+  uint32_t row[kSub];
+  uint32_t idx[kSub];
+  uint32_t src[kSub];       // payload offset relative to the sub-chunk's first byte
+  uint32_t bpre[kSub + 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
+  uint16_t dig[kSub];
+  uint16_t wc[kMaxFanout * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
+};
+
+// Ranks each lane's cells stably by digit (ballot multisplit per 64-cell
+// round, counters per (digit, wave)), scans the counters digit-major and
+// stores the cells in sorted order. Registers: per-lane arrays of kItems cells
+// in wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
+__device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint32_t n,
+                                         const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
+                                         const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
+                                         const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems]) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t E = F * kNW;
+  for (uint32_t e = threadIdx.x; e < E; e += kBlock) L.wc[e] = 0;
+  __syncthreads();
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    const bool act = i < n;
+    const uint32_t d = act ? dg[r] : 0u;
+    const uint64_t peers = match_peers(d, act, dbits);
+    rank[r] = 0;
+    if (act) {
+      const uint32_t below = popc_below(peers);
+      const uint32_t old = L.wc[d * kNW + w];
+      if (below == 0) L.wc[d * kNW + w] = (uint16_t)(old + (uint32_t)__popcll(peers));
+      rank[r] = old + below;
+    }
+  }
+  __syncthreads();
+  // digit-major exclusive scan of the (digit, wave) counters
+  {
+    const uint32_t per = (E + kBlock - 1) / kBlock;
+    const uint32_t e0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t e = e0; e < e0 + per && e < E; ++e) s += L.wc[e];
+    __shared__ uint32_t red[kNW + 1];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kNW>(s, red, tot);
+    for (uint32_t e = e0; e < e0 + per && e < E; ++e) {
+      const uint32_t v = L.wc[e];
+      L.wc[e] = (uint16_t)ex;
+      ex += v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    if (i < n) {
+      const uint32_t p = (uint32_t)L.wc[dg[r] * kNW + w] + rank[r];
+      L.key[p] = key[r];
+      L.sz[p] = sz[r];
+      L.row[p] = row[r];
+      L.idx[p] = idx[r];
+      L.src[p] = src[r];
+      L.dig[p] = (uint16_t)dg[r];
+    }
+  }
+  __syncthreads();
+  // sizes in sorted order -> exclusive byte prefix
+  {
+    constexpr int kPer = kSub / kBlock;
+    const uint32_t p0 = threadIdx.x * kPer;
+    uint32_t v[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      v[q] = (p0 + q < n) ? L.sz[p0 + q] : 0u;
+      s += v[q];
+    }
+    __shared__ uint32_t red2[kNW + 1];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kNW>(s, red2, tot);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (p0 + q < n) L.bpre[p0 + q] = ex;
+      ex += v[q];
+    }
+    if (threadIdx.x == 0) L.bpre[n] = tot;
+  }
+  __syncthreads();
+}
+
+// Exclusive prefix (in cell order i = wave*kWaveCells + r*64 + lane) of the
+// per-cell sizes of a sub-chunk. Returns the sub-chunk total.
+__device__ __forceinline__ uint32_t sub_src_prefix(const uint32_t (&sz)[kItems], uint32_t (&src)[kItems],
+                                                   uint32_t* red) {
+  const uint32_t w = threadIdx.x / kWave;
+  uint32_t carry = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t inc = wave_incl_scan_u32(sz[r]) + carry;
+    src[r] = inc - sz[r];
+    carry = wave_bcast(inc, kWave - 1);
+  }
+  if (lane_id() == 0) red[w] = carry;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+  for (uint32_t q = 0; q < (uint32_t)kNW; ++q) {
+    const uint32_t t = red[q];
+    if (q < w) wbase += t;
+    tot += t;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) src[r] += wbase;
+  __syncthreads();
+  return tot;
+}
+
+// ----------------------------------------------------------------------------- pass: scatter
+
+__global__ __launch_bounds__(kBlock) void k_pass_scatter(PassArgs a) {
+  __shared__ SortLds L;
+  __shared__ uint64_t s_rc[kMaxFanout];  // running destination cell per digit
+  __shared__ uint64_t s_rb[kMaxFanout];  // running destination byte per digit
+  __shared__ int64_t s_lb[kMaxParts + 1];
+  __shared__ Seg s_seg;
+  __shared__ uint32_t s_si, s_rlo, s_rhi, s_first_row, s_last_row;
+  __shared__ uint32_t s_red[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
+  if (tile >= a.tstart[a.nseg]) return;
+  if (threadIdx.x == 0) {
+    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
+    s_si = si;
+    s_seg = a.segs[si];
+  }
+  __syncthreads();
+  const Seg sg = s_seg;
+  const uint32_t si = s_si;
+  const ItemDev* it = &a.items[sg.item];
+  const uint32_t R = (uint32_t)it->n_parts;
+  const uint32_t F = seg_fanout(sg, R);
+  const int dbits = ceil_log2(F);
+  const int ow = a.offset_width;
+  const uint64_t j = tile - a.tstart[si];
+  const uint64_t nt = a.tstart[si + 1] - a.tstart[si];
+  const uint64_t hb = a.hstart[si];
+  const uint64_t c_begin = j * a.tile_cells;
+  const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
+  const bool pass0 = a.pass == 0;
+  const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
+  const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
+
+  if (sg.mode)
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = it->bounds[i];
+  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+    s_rc[d] = a.ocnt[hb + (uint64_t)d * nt + j];
+    s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
+  }
+  if (pass0 && threadIdx.x < 2) {
+    const uint64_t k = kbase + (threadIdx.x == 0 ? c_begin : c_end - 1);
+    const uint32_t r = row_of(it->row_ptr, ow, k, 0u, (uint32_t)(it->n_rows - 1));
+    if (threadIdx.x == 0) s_rlo = r;
+    else s_rhi = r;
+  }
+  __syncthreads();
+  const uint32_t rlo = pass0 ? s_rlo : 0u, rhi = pass0 ? s_rhi : 0u;
+  // byte offset (source side) of the current sub-chunk's first cell
+  uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+
+  for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
+    const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
+    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
+    uint64_t sub_base;
+    if (pass0) {
+      sub_base = (uint64_t)ld_off(it->poff, kbase + c0, ow);
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = w * kWaveCells + r * kWave + lane;
+        key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; src[r] = 0; dg[r] = 0;
+        if (i < n) {
+          const uint64_t k = kbase + c0 + i;
+          key[r] = (uint32_t)it->col[k];
+          const int64_t p0 = ld_off(it->poff, k, ow);
+          sz[r] = (uint32_t)(ld_off(it->poff, k + 1, ow) - p0);
+          src[r] = (uint32_t)((uint64_t)p0 - sub_base);
+          row[r] = row_of(it->row_ptr, ow, k, rlo, rhi);
+          idx[r] = (uint32_t)k;
+        }
+      }
+    } else {
+      sub_base = src_sub;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = w * kWaveCells + r * kWave + lane;
+        key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; dg[r] = 0;
+        if (i < n) {
+          const uint2 ks = a.ks_in[sg.cell0 + c0 + i];
+          const uint2 rk = a.rk_in[sg.cell0 + c0 + i];
+          key[r] = ks.x; sz[r] = ks.y; row[r] = rk.x; idx[r] = rk.y;
+        }
+      }
+      const uint32_t tot = sub_src_prefix(sz, src, s_red);
+      src_sub += tot;
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      if (i < n) dg[r] = digit_of(key[r], sg, s_lb, R);
+      if (track_xfer && i == 0) s_first_row = row[r];
+      if (track_xfer && i == n - 1) s_last_row = row[r];
+    }
+    sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
+
+    const uint8_t* src_base = pass0 ? it->payload + sub_base : a.pay_in + sub_base;
+    bool xfer_per_cell = false;
+    uint32_t src_part = 0;
+    if (track_xfer) {
+      src_part = owner_of(s_lb, R, (int64_t)s_first_row);
+      xfer_per_cell = owner_of(s_lb, R, (int64_t)s_last_row) != src_part;
+    }
+    // write the sorted cells at their digit's running destination
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = r * kBlock + threadIdx.x;
+      if (i < n) {
+        const uint32_t d = L.dig[i];
+        const uint32_t ds = L.wc[d * kNW];
+        const uint64_t cd = s_rc[d] + (i - ds);
+        const uint64_t bd = s_rb[d] + (L.bpre[i] - L.bpre[ds]);
+        const uint32_t csz = L.sz[i];
+        a.ks_out[cd] = make_uint2(L.key[i], csz);
+        a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+        if (csz) copy_bytes(a.pay_out + bd, src_base + L.src[i], csz);
+        if (xfer_per_cell) {
+          const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
+          const uint32_t dp = d >> sg.bits;
+          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
+          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)csz);
+        }
+      }
+    }
+    if (track_xfer && !xfer_per_cell) {
+      const uint32_t sub = 1u << sg.bits;
+      for (uint32_t p = threadIdx.x; p < R; p += kBlock) {
+        const uint32_t d0 = p << sg.bits, d1 = d0 + sub;
+        const uint32_t i0 = L.wc[d0 * kNW];
+        const uint32_t i1 = d1 < F ? L.wc[d1 * kNW] : n;
+        if (i1 > i0) {
+          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)src_part * R + p],
+                    (unsigned long long)(i1 - i0));
+          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)src_part * R + p],
+                    (unsigned long long)(L.bpre[i1] - L.bpre[i0]));
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+      const uint32_t i0 = L.wc[d * kNW];
+      const uint32_t i1 = d + 1 < F ? L.wc[(d + 1) * kNW] : n;
+      s_rc[d] += i1 - i0;
+      s_rb[d] += L.bpre[i1] - L.bpre[i0];
+    }
+    __syncthreads();
+  }
+}
+
+// ----------------------------------------------------------------------------- finish
+
+__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs a) {
+  __shared__ SortLds L;
+  __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
+  __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
+  __shared__ uint32_t s_red[kNW + 1];
+  __shared__ uint64_t s_red64[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const Seg sg = a.buckets[blockIdx.x];
+  const ItemDev* it = &a.items[sg.item];
+  const int ow = a.offset_width;
+  const uint32_t nc = sg.key_hi - sg.key_lo;
+  if (nc == 0) return;
+  const int dbits = ceil_log2(nc);
+  const uint64_t out_cell0 = sg.cell0 - it->cell_base;
+  const uint64_t out_byte0 = sg.byte0 - it->byte_base;
+  const uint32_t len = sg.len;
+  const bool multi = len > (uint32_t)kSub;
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  void* t_row_ptr = it->t_row_ptr;
+
+  if (multi) {
+    for (uint32_t c = threadIdx.x; c < nc; c += kBlock) {
+      s_cc[c] = 0;
+      s_cb[c] = 0;
+    }
+    __syncthreads();
+    for (uint32_t c = threadIdx.x; c < len; c += kBlock) {
+      const uint2 ks = a.ks_in[sg.cell0 + c];
+      uint32_t d = ks.x - sg.key_lo;
+      d = d < nc ? d : nc - 1;
+      atomicAdd(&s_cc[d], 1u);
+      atomicAdd((unsigned long long*)&s_cb[d], (unsigned long long)ks.y);
+    }
+    __syncthreads();
+    const uint32_t per = (nc + kBlock - 1) / kBlock;
+    const uint32_t e0 = threadIdx.x * per;
+    uint32_t s = 0;
+    uint64_t sb = 0;
+    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
+      s += s_cc[e];
+      sb += s_cb[e];
+    }
+    uint32_t tot;
+    uint64_t totb;
+    uint32_t ex = block_excl_scan<kNW>(s, s_red, tot);
+    uint64_t exb = block_excl_scan<kNW>(sb, s_red64, totb);
+    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
+      const uint32_t v = s_cc[e];
+      const uint64_t vb = s_cb[e];
+      s_cc[e] = ex;
+      s_cb[e] = exb;
+      st_off(t_row_ptr, (uint64_t)sg.key_lo + e, (int64_t)(out_cell0 + ex), ow);
+      ex += v;
+      exb += vb;
+    }
+    __syncthreads();
+  }
+
+  uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
+  for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
+    const uint32_t n = min((uint32_t)kSub, len - c0);
+    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; dg[r] = 0;
+      if (i < n) {
+        const uint2 ks = a.ks_in[sg.cell0 + c0 + i];
+        const uint2 rk = a.rk_in[sg.cell0 + c0 + i];
+        key[r] = ks.x; sz[r] = ks.y; row[r] = rk.x; idx[r] = rk.y;
+        const uint32_t d = ks.x - sg.key_lo;
+        dg[r] = d < nc ? d : nc - 1;
+      }
+    }
+    const uint32_t subtot = sub_src_prefix(sz, src, s_red);
+    sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
+    if (!multi) {
+      // one sub-chunk: its digit scan is the column layout of the whole bucket
+      for (uint32_t c = threadIdx.x; c < nc; c += kBlock)
+        st_off(t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kNW]), ow);
+    }
+    const uint8_t* src_base = a.pay_in + src_sub;
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = r * kBlock + threadIdx.x;
+      if (i < n) {
+        uint64_t p, b;
+        if (multi) {
+          const uint32_t d = L.dig[i];
+          const uint32_t ds = L.wc[d * kNW];
+          p = out_cell0 + s_cc[d] + (i - ds);
+          b = out_byte0 + s_cb[d] + (L.bpre[i] - L.bpre[ds]);
+        } else {
+          p = out_cell0 + i;
+          b = out_byte0 + L.bpre[i];
+        }
+        it->t_col[p] = (int32_t)L.row[i];
+        if (it->perm) it->perm[p] = L.idx[i];
+        st_off(it->t_poff, p, (int64_t)b, ow);
+        const uint32_t csz = L.sz[i];
+        if (csz) copy_bytes(it->t_payload + b, src_base + L.src[i], csz);
+      }
+    }
+    __syncthreads();
+    if (multi) {
+      for (uint32_t d = threadIdx.x; d < nc; d += kBlock) {
+        const uint32_t i0 = L.wc[d * kNW];
+        const uint32_t i1 = d + 1 < nc ? L.wc[(d + 1) * kNW] : n;
+        s_cc[d] += i1 - i0;
+        s_cb[d] += L.bpre[i1] - L.bpre[i0];
+      }
+      __syncthreads();
+    }
+    src_sub += subtot;
+    if (len == 0) break;
+  }
+}
+
+// ----------------------------------------------------------------------------- tails
+
+__global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int32_t* abort_flag,
+                                                int ow) {
+  __shared__ uint64_t red[1024 / kWave + 1];
+  if (aborted(abort_flag)) return;
+  const ItemDev& it = items[blockIdx.x];
+  if (threadIdx.x == 0) {
+    st_off(it.t_row_ptr, (uint64_t)it.n_cols, it.nnz, ow);
+    st_off(it.t_poff, (uint64_t)it.nnz, it.payload_bytes, ow);
+  }
+  if (!it.part_mode || !it.xfer_cells) return;
+  const uint32_t R = (uint32_t)it.n_parts;
+  // cells / bytes received by each partition s: column sums of X and B
+  uint64_t cells = 0, bytes = 0;
+  const uint32_t s = threadIdx.x;
+  if (s < R)
+    for (uint32_t r = 0; r < R; ++r) {
+      cells += (uint64_t)it.xfer_cells[(uint64_t)r * R + s];
+      bytes += (uint64_t)it.xfer_bytes[(uint64_t)r * R + s];
+    }
+  uint64_t tc, tb;
+  const uint64_t ec = block_excl_scan<1024 / kWave>(cells, red, tc);
+  const uint64_t eb = block_excl_scan<1024 / kWave>(bytes, red, tb);
+  if (s < R) {
+    if (it.part_cell_off) it.part_cell_off[s] = (int64_t)ec;
+    if (it.part_byte_off) it.part_byte_off[s] = (int64_t)eb;
+  }
+  if (s == 0) {
+    if (it.part_cell_off) it.part_cell_off[R] = (int64_t)tc;
+    if (it.part_byte_off) it.part_byte_off[R] = (int64_t)tb;
+  }
+  if (s < R && it.sdispls) {  // row s of X scanned along destinations
+    int64_t acc = 0;
+    for (uint32_t d = 0; d < R; ++d) {
+      it.sdispls[(uint64_t)s * R + d] = acc;
+      acc += it.xfer_cells[(uint64_t)s * R + d];
+    }
+  }
+  if (s < R && it.rdispls) {  // column s of X scanned along sources
+    int64_t acc = 0;
+    for (uint32_t r = 0; r < R; ++r) {
+      it.rdispls[(uint64_t)s * R + r] = acc;
+      acc += it.xfer_cells[(uint64_t)r * R + s];
+    }
+  }
+}
+
+__global__ void k_status_out(const int32_t* item_status, const int32_t* abort_flag, uint32_t n,
+                             int32_t* d_status) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t s = item_status[i];
+  d_status[i] = (s == MGT_OK && *abort_flag) ? MGT_ECANCELED : s;
+}
+
+// ----------------------------------------------------------------------------- launchers
+
+static inline dim3 grid1(uint64_t n) { return dim3((unsigned)n); }
+
+hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,
+                       uint32_t* hsize0, int32_t* item_status, int32_t* abort_flag,
+                       uint32_t tile_cells, hipStream_t s) {
+  hipLaunchKernelGGL(k_init, grid1(n_items), dim3(kBlock), 0, s, items, n_items, segs0, tiles0,
+                     hsize0, item_status, abort_flag, tile_cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
+                           int32_t* item_status, int32_t* abort_flag, int32_t ow, hipStream_t s) {
+  uint64_t gx = (max_len + 1 + kBlock * 16 - 1) / (kBlock * 16);
+  gx = gx < 1 ? 1 : (gx > 2048 ? 2048 : gx);
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)gx, n_items), dim3(kBlock), 0, s, items,
+                     item_status, abort_flag, ow);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* in0, uint64_t* out0, const uint32_t* in1, uint64_t* out1,
+                       const uint64_t* n_dev, uint64_t n_max, uint64_t* block_sums, hipStream_t s) {
+  const uint64_t nb = (n_max + kScanBlock - 1) / kScanBlock;
+  const uint64_t cap = nb + 1;
+  if (nb) {
+    hipLaunchKernelGGL(k_scan_reduce, grid1(nb), dim3(kBlock), 0, s, in0, in1, n_dev, n_max,
+                       block_sums, cap);
+  }
+  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, s, n_dev, n_max, block_sums, cap, out0,
+                     out1);
+  if (nb) {
+    hipLaunchKernelGGL(k_scan_down, grid1(nb), dim3(kBlock), 0, s, in0, out0, in1, out1, n_dev,
+                       n_max, block_sums, cap);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s) {
+  if (a.g8) hipLaunchKernelGGL(k_pass_hist, grid1(a.g8), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
+  if (a.g8) hipLaunchKernelGGL(k_pass_scatter, grid1(a.g8), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
+  if (a.nseg) hipLaunchKernelGGL(k_children, grid1(a.nseg), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
+  if (a.nbuckets) hipLaunchKernelGGL(k_finish, grid1(a.nbuckets), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* abort_flag,
+                        int32_t ow, hipStream_t s) {
+  hipLaunchKernelGGL(k_tails, grid1(n_items), dim3(1024), 0, s, items, abort_flag, ow);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_out(const int32_t* item_status, const int32_t* abort_flag,
+                             uint32_t n_items, int32_t* d_status, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_out, dim3((n_items + 255) / 256), dim3(256), 0, s, item_status,
+                     abort_flag, n_items, d_status);
+  return hipGetLastError();
+}
+
+}  // namespace mgt

@@ -1,0 +1,675 @@
+// Host runtime of libmgt: descriptor checks, digit schedules, workspace
+// layout and the launch sequence behind the C ABI declared in include/mgt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mgt.h"
+#include "kernels.h"
+#include "mgt_internal.h"
+
+using namespace mgt;
+
+namespace {
+
+constexpr uint32_t kTileCells = 16384;    // cells per partition-pass tile (multiple of kSub)
+constexpr int kMaxBitsPerPass = 9;        // fan-out 512 per bits-mode pass
+constexpr uint32_t kMaxPartFanout = 512;  // preferred fan-out of the partition pass
+constexpr int kMaxItems = 65535;
+static_assert(kTileCells % kSub == 0, "tile geometry");
+
+int ceil_log2_u64(uint64_t x) {
+  int b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+int floor_log2_u64(uint64_t x) {
+  int b = -1;
+  while (x) { x >>= 1; ++b; }
+  return b;
+}
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// Digit schedule of one matrix.
+struct Sched {
+  int n_levels = 1;
+  int bits[kMaxLevels] = {0, 0, 0, 0};
+  int key_bits = 0;
+  int part_mode = 0;
+  int finish_bits = 0;
+};
+
+// Number of passes needed for `B` bits when the first pass may take `first_cap`.
+int passes_for(int B, int first_cap) {
+  if (B <= 0) return 1;
+  int rest = B - std::min(B, first_cap);
+  return 1 + (rest + kMaxBitsPerPass - 1) / kMaxBitsPerPass;
+}
+
+Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned) {
+  Sched s;
+  uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
+  if (partitioned) {
+    width = 1;
+    for (int32_t r = 0; r < R; ++r) width = std::max<uint64_t>(width, (uint64_t)(bounds[r + 1] - bounds[r]));
+    s.part_mode = 1;
+  }
+  const int K = ceil_log2_u64(width);
+  s.key_bits = K;
+  // Finish buckets of ~2 * kSub cells: 2^fb columns at nnz / n_cols cells each.
+  int fb_ideal = 0;
+  if (nnz > 0 && n_cols > 0) {
+    const double per_col = (double)nnz / (double)n_cols;
+    fb_ideal = floor_log2_u64((uint64_t)std::max(1.0, 2.0 * kSub / per_col));
+  } else {
+    fb_ideal = kMaxFinishBits;
+  }
+  fb_ideal = std::min(std::max(fb_ideal, 0), std::min(kMaxFinishBits, K));
+  const int first_cap = partitioned
+      ? (R <= (int32_t)kMaxPartFanout ? floor_log2_u64(kMaxPartFanout / (uint32_t)R) : 0)
+      : kMaxBitsPerPass;
+  // Fewest passes first, then the smallest finish width that achieves them.
+  int best_fb = fb_ideal, best_L = 1 << 30;
+  for (int fb = fb_ideal; fb <= std::min(kMaxFinishBits, K); ++fb) {
+    const int L = passes_for(K - fb, first_cap);
+    if (L < best_L) { best_L = L; best_fb = fb; }
+  }
+  if (K <= fb_ideal) { best_fb = K; best_L = 1; }
+  const int B = K - best_fb;
+  s.finish_bits = best_fb;
+  s.n_levels = best_L;
+  int rest = B;
+  s.bits[0] = std::min(B, first_cap);
+  if (!partitioned && best_L > 1) s.bits[0] = (B + best_L - 1) / best_L;  // spread evenly
+  rest -= s.bits[0];
+  for (int l = 1; l < best_L; ++l) {
+    const int left = best_L - l;
+    s.bits[l] = (rest + left - 1) / left;
+    rest -= s.bits[l];
+  }
+  return s;
+}
+
+uint32_t fanout(const Sched& s, int l, int32_t R) {
+  return (l == 0 && s.part_mode) ? ((uint32_t)R << s.bits[0]) : (1u << s.bits[l]);
+}
+
+// One matrix of a call, as the host sees it.
+struct HostItem {
+  mgt_desc d;
+  Sched s;
+  const int64_t* bounds;  // host
+  ItemDev dev;
+};
+
+// Workspace layout of one call.
+struct Layout {
+  uint32_t n_items = 0;
+  int L = 1;
+  uint64_t total_nnz = 0, total_bytes = 0, total_bounds = 0;
+  uint64_t nseg[kMaxLevels + 1] = {};
+  uint64_t tiles_max[kMaxLevels] = {};
+  uint64_t hist_max = 0, tiles_all_max = 0, scan_max = 0;
+  // offsets
+  uint64_t o_items, o_status, o_abort, o_bounds;
+  uint64_t o_segs[kMaxLevels + 1], o_tcnt[kMaxLevels], o_hsz[kMaxLevels], o_tstart[kMaxLevels],
+      o_hstart[kMaxLevels];
+  uint64_t o_hcnt, o_hbyt, o_ocnt, o_obyt, o_ttot, o_tsrc, o_scan;
+  uint64_t o_ks[2], o_rk[2], o_pay[2];
+  uint64_t bytes = 0;
+};
+
+Layout make_layout(std::vector<HostItem>& items) {
+  Layout y;
+  y.n_items = (uint32_t)items.size();
+  int L = 1;
+  for (auto& it : items) L = std::max(L, it.s.n_levels);
+  y.L = L;
+  // pad every schedule to L passes (extra passes have 0 bits: copies)
+  for (auto& it : items) {
+    for (int l = it.s.n_levels; l < L; ++l) it.s.bits[l] = 0;
+    it.s.n_levels = L;
+  }
+  uint64_t cell = 0, byte = 0, tiles0 = 0;
+  for (auto& it : items) {
+    it.dev.cell_base = cell;
+    it.dev.byte_base = byte;
+    cell += (uint64_t)it.d.nnz;
+    byte += (uint64_t)it.d.payload_bytes;
+    y.total_bounds += (uint64_t)it.d.n_parts + 1;
+  }
+  y.total_nnz = cell;
+  y.total_bytes = byte;
+  for (int l = 0; l <= L; ++l) y.nseg[l] = 0;
+  for (auto& it : items) {
+    uint64_t ns = 1;
+    for (int l = 0; l <= L; ++l) {
+      it.dev.seg_base[l] = y.nseg[l];
+      y.nseg[l] += ns;
+      if (l < L) ns *= fanout(it.s, l, it.d.n_parts);
+    }
+    const uint64_t t0 = ((uint64_t)it.d.nnz + kTileCells - 1) / kTileCells;
+    it.dev.tile_base = tiles0;
+    tiles0 += t0;
+  }
+  // per-pass tile and histogram bounds
+  for (int l = 0; l < L; ++l) {
+    uint64_t tiles = 0, hist = 0;
+    for (auto& it : items) {
+      uint64_t ns = it.dev.seg_base[l];  // not used directly
+      (void)ns;
+      uint64_t segs_item = 1;
+      for (int q = 0; q < l; ++q) segs_item *= fanout(it.s, q, it.d.n_parts);
+      const uint64_t t = ((uint64_t)it.d.nnz + kTileCells - 1) / kTileCells + (l ? segs_item : 0);
+      tiles += t;
+      hist += t * fanout(it.s, l, it.d.n_parts);
+    }
+    y.tiles_max[l] = tiles;
+    y.tiles_all_max = std::max(y.tiles_all_max, tiles);
+    y.hist_max = std::max(y.hist_max, hist);
+  }
+  y.scan_max = std::max<uint64_t>(y.hist_max, y.tiles_all_max);
+  for (int l = 0; l <= L; ++l) y.scan_max = std::max(y.scan_max, y.nseg[l]);
+
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  y.o_items = take(sizeof(ItemDev) * y.n_items);
+  y.o_status = take(4ull * y.n_items);
+  y.o_abort = take(64);
+  y.o_bounds = take(8ull * y.total_bounds);
+  for (int l = 0; l <= L; ++l) y.o_segs[l] = take(sizeof(Seg) * y.nseg[l]);
+  for (int l = 0; l < L; ++l) {
+    y.o_tcnt[l] = take(4ull * y.nseg[l]);
+    y.o_hsz[l] = take(4ull * y.nseg[l]);
+    y.o_tstart[l] = take(8ull * (y.nseg[l] + 1));
+    y.o_hstart[l] = take(8ull * (y.nseg[l] + 1));
+  }
+  y.o_hcnt = take(4ull * y.hist_max);
+  y.o_hbyt = take(4ull * y.hist_max);
+  y.o_ocnt = take(8ull * (y.hist_max + 1));
+  y.o_obyt = take(8ull * (y.hist_max + 1));
+  y.o_ttot = take(4ull * y.tiles_all_max);
+  y.o_tsrc = take(8ull * (y.tiles_all_max + 1));
+  y.o_scan = take(scan_scratch_bytes(y.scan_max));
+  const int nbuf = L >= 2 ? 2 : 1;
+  for (int b = 0; b < 2; ++b) {
+    if (b < nbuf) {
+      y.o_ks[b] = take(8ull * y.total_nnz);
+      y.o_rk[b] = take(8ull * y.total_nnz);
+      y.o_pay[b] = take(y.total_bytes + 16);
+    } else {
+      y.o_ks[b] = y.o_ks[0];
+      y.o_rk[b] = y.o_rk[0];
+      y.o_pay[b] = y.o_pay[0];
+    }
+  }
+  y.bytes = o + 256;
+  return y;
+}
+
+int check_desc(const mgt_desc* d, bool need_bounds) {
+  if (!d) return MGT_EINVAL;
+  if (d->n_rows < 0 || d->n_cols < 0 || d->nnz < 0 || d->payload_bytes < 0) return MGT_EINVAL;
+  if (d->offset_width != 4 && d->offset_width != 8) return MGT_EINVAL;
+  if (d->n_rows >= (1ll << 31) || d->n_cols >= (1ll << 31)) return MGT_EUNSUPPORTED;
+  if (d->nnz >= (1ll << 32)) return MGT_EUNSUPPORTED;
+  if (d->offset_width == 4 && (d->nnz >= (1ll << 31) || d->payload_bytes >= (1ll << 31)))
+    return MGT_EUNSUPPORTED;
+  if (d->nnz > 0 && (d->n_rows == 0 || d->n_cols == 0)) return MGT_EINVAL;
+  if (d->n_parts < 1 || d->n_parts > kMaxParts) return MGT_EINVAL;
+  if (d->n_parts > 1 || need_bounds) {
+    if (!d->part_bounds) return MGT_EINVAL;
+    if (d->n_parts > 1 && d->n_rows != d->n_cols) return MGT_EINVAL;
+    if (d->part_bounds[0] != 0 || d->part_bounds[d->n_parts] != d->n_rows) return MGT_EINVAL;
+    for (int32_t r = 0; r < d->n_parts; ++r)
+      if (d->part_bounds[r + 1] < d->part_bounds[r]) return MGT_EINVAL;
+  }
+  return MGT_OK;
+}
+
+struct Timing {
+  std::vector<hipEvent_t> ev;
+  std::vector<const char*> names;
+  int used = 0;
+};
+
+}  // namespace
+
+struct mgt_plan_s {
+  bool batch = false;
+  mgt_desc desc{};
+  std::vector<int64_t> bounds;
+  mgt_batch_limits lim{};
+  uint32_t flags = 0;
+  // single-matrix plans: the two schedules and their workspace
+  size_t ws_plain = 0, ws_part = 0;
+  // upload staging (pinned) and its completion event
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  Timing timing;
+};
+
+namespace {
+
+int ensure_staging(mgt_plan_s* p, size_t bytes) {
+  if (!p->upload_done &&
+      hipEventCreateWithFlags(&p->upload_done, hipEventDisableTiming) != hipSuccess)
+    return MGT_EHIP;
+  if (p->upload_pending) {
+    if (hipEventSynchronize(p->upload_done) != hipSuccess) return MGT_EHIP;
+    p->upload_pending = false;
+  }
+  if (p->staging_bytes >= bytes) return MGT_OK;
+  if (p->staging) hipHostFree(p->staging);
+  p->staging = nullptr;
+  p->staging_bytes = 0;
+  if (hipHostMalloc(&p->staging, bytes, hipHostMallocDefault) != hipSuccess) return MGT_ENOMEM;
+  p->staging_bytes = bytes;
+  return MGT_OK;
+}
+
+void time_mark(mgt_plan_s* p, hipStream_t s, const char* name) {
+  if (!(p->flags & MGT_DEBUG_TIMING)) return;
+  Timing& t = p->timing;
+  if (t.used >= (int)t.ev.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    t.ev.push_back(e);
+    t.names.push_back(name);
+  }
+  t.names[t.used] = name;
+  hipEventRecord(t.ev[t.used], s);
+  ++t.used;
+}
+
+#define MGT_HIP(x)                          \
+  do {                                      \
+    if ((x) != hipSuccess) return MGT_EHIP; \
+  } while (0)
+
+// Runs the whole pipeline for `items` (already scheduled and laid out).
+int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, int32_t* d_status,
+        hipStream_t s) {
+  uint8_t* W = (uint8_t*)ws;
+  const int ow = items.empty() ? 8 : items[0].d.offset_width;
+  const uint32_t n = y.n_items;
+  // 1. upload items + bounds through the pinned staging buffer
+  const size_t up_bytes = y.o_bounds + 8ull * y.total_bounds;
+  int st = ensure_staging(p, up_bytes);
+  if (st != MGT_OK) return st;
+  uint8_t* H = (uint8_t*)p->staging;
+  int64_t* hb = (int64_t*)(H + y.o_bounds);
+  uint64_t bo = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    HostItem& it = items[i];
+    ItemDev& d = it.dev;
+    d.n_rows = it.d.n_rows;
+    d.n_cols = it.d.n_cols;
+    d.nnz = it.d.nnz;
+    d.payload_bytes = it.d.payload_bytes;
+    d.n_parts = it.d.n_parts;
+    d.n_levels = it.s.n_levels;
+    for (int l = 0; l < kMaxLevels; ++l) d.bits[l] = it.s.bits[l];
+    d.key_bits = it.s.key_bits;
+    d.part_mode = it.s.part_mode;
+    d.status_index = (int32_t)i;
+    d.bounds = (const int64_t*)(W + y.o_bounds) + bo;
+    for (int32_t r = 0; r <= it.d.n_parts; ++r)
+      hb[bo + r] = (it.d.n_parts == 1 && !it.bounds) ? (r ? it.d.n_rows : 0) : it.bounds[r];
+    bo += (uint64_t)it.d.n_parts + 1;
+    std::memcpy(H + y.o_items + sizeof(ItemDev) * i, &d, sizeof(ItemDev));
+  }
+  time_mark(p, s, "start");
+  MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
+  MGT_HIP(hipEventRecord(p->upload_done, s));
+  p->upload_pending = true;
+
+  const ItemDev* d_items = (const ItemDev*)(W + y.o_items);
+  int32_t* d_item_status = (int32_t*)(W + y.o_status);
+  int32_t* d_abort = (int32_t*)(W + y.o_abort);
+  auto segs = [&](int l) { return (Seg*)(W + y.o_segs[l]); };
+  auto tcnt = [&](int l) { return (uint32_t*)(W + y.o_tcnt[l]); };
+  auto hsz = [&](int l) { return (uint32_t*)(W + y.o_hsz[l]); };
+  auto tstart = [&](int l) { return (uint64_t*)(W + y.o_tstart[l]); };
+  auto hstart = [&](int l) { return (uint64_t*)(W + y.o_hstart[l]); };
+  uint32_t* hcnt = (uint32_t*)(W + y.o_hcnt);
+  uint32_t* hbyt = (uint32_t*)(W + y.o_hbyt);
+  uint64_t* ocnt = (uint64_t*)(W + y.o_ocnt);
+  uint64_t* obyt = (uint64_t*)(W + y.o_obyt);
+  uint32_t* ttot = (uint32_t*)(W + y.o_ttot);
+  uint64_t* tsrc = (uint64_t*)(W + y.o_tsrc);
+  uint64_t* scan = (uint64_t*)(W + y.o_scan);
+
+  MGT_HIP(launch_init(d_items, n, segs(0), tcnt(0), hsz(0), d_item_status, d_abort, kTileCells, s));
+  if (p->flags & MGT_VALIDATE) {
+    uint64_t max_len = 0;
+    for (auto& it : items) max_len = std::max<uint64_t>(max_len, (uint64_t)std::max(it.d.n_rows, it.d.nnz));
+    MGT_HIP(launch_validate(d_items, n, max_len, d_item_status, d_abort, ow, s));
+  }
+  MGT_HIP(launch_scan(tcnt(0), tstart(0), hsz(0), hstart(0), nullptr, y.nseg[0], scan, s));
+  time_mark(p, s, "init");
+
+  const int L = y.L;
+  for (int l = 0; l < L; ++l) {
+    PassArgs a{};
+    a.items = d_items;
+    a.segs = segs(l);
+    a.nseg = (uint32_t)y.nseg[l];
+    a.pass = (uint32_t)l;
+    a.tstart = tstart(l);
+    a.hstart = hstart(l);
+    const int bi = (l - 1) & 1, bo2 = l & 1;
+    a.ks_in = l ? (const uint2*)(W + y.o_ks[bi]) : nullptr;
+    a.rk_in = l ? (const uint2*)(W + y.o_rk[bi]) : nullptr;
+    a.pay_in = l ? (const uint8_t*)(W + y.o_pay[bi]) : nullptr;
+    a.ks_out = (uint2*)(W + y.o_ks[bo2]);
+    a.rk_out = (uint2*)(W + y.o_rk[bo2]);
+    a.pay_out = (uint8_t*)(W + y.o_pay[bo2]);
+    a.hcnt = hcnt;
+    a.hbyt = hbyt;
+    a.ttot = ttot;
+    a.ocnt = ocnt;
+    a.obyt = obyt;
+    a.tsrc = tsrc;
+    a.item_status = d_item_status;
+    a.abort_flag = d_abort;
+    a.g8 = align_up(y.tiles_max[l], 8);
+    a.tile_cells = kTileCells;
+    a.offset_width = ow;
+    MGT_HIP(launch_pass_hist(a, s));
+    time_mark(p, s, "hist");
+    const uint64_t nseg = y.nseg[l];
+    MGT_HIP(launch_scan(hcnt, ocnt, hbyt, obyt, hstart(l) + nseg, y.hist_max, scan, s));
+    if (l > 0) MGT_HIP(launch_scan(ttot, tsrc, nullptr, nullptr, tstart(l) + nseg, y.tiles_all_max, scan, s));
+    ChildArgs c{};
+    c.items = d_items;
+    c.segs = segs(l);
+    c.nseg = (uint32_t)nseg;
+    c.pass = (uint32_t)l;
+    c.tstart = tstart(l);
+    c.hstart = hstart(l);
+    c.ocnt = ocnt;
+    c.obyt = obyt;
+    c.children = segs(l + 1);
+    c.child_tiles = (l + 1 < L) ? tcnt(l + 1) : nullptr;
+    c.child_hsize = (l + 1 < L) ? hsz(l + 1) : nullptr;
+    c.tile_cells = kTileCells;
+    c.abort_flag = d_abort;
+    MGT_HIP(launch_children(c, s));
+    if (l + 1 < L)
+      MGT_HIP(launch_scan(tcnt(l + 1), tstart(l + 1), hsz(l + 1), hstart(l + 1), nullptr, y.nseg[l + 1], scan, s));
+    time_mark(p, s, "scan");
+    MGT_HIP(launch_pass_scatter(a, s));
+    time_mark(p, s, "scatter");
+  }
+  FinishArgs f{};
+  f.items = d_items;
+  f.buckets = segs(L);
+  f.nbuckets = (uint32_t)y.nseg[L];
+  const int bl = (L - 1) & 1;
+  f.ks_in = (const uint2*)(W + y.o_ks[bl]);
+  f.rk_in = (const uint2*)(W + y.o_rk[bl]);
+  f.pay_in = (const uint8_t*)(W + y.o_pay[bl]);
+  f.abort_flag = d_abort;
+  f.offset_width = ow;
+  MGT_HIP(launch_finish(f, s));
+  time_mark(p, s, "finish");
+  MGT_HIP(launch_tails(d_items, n, d_abort, ow, s));
+  if (d_status) MGT_HIP(launch_status_out(d_item_status, d_abort, n, d_status, s));
+  time_mark(p, s, "tails");
+  return MGT_OK;
+}
+
+void fill_outputs(ItemDev& d, const void* row_ptr, const int32_t* col, const void* payload_off,
+                  const uint8_t* payload, void* t_row_ptr, int32_t* t_col, void* t_payload_off,
+                  uint8_t* t_payload, uint32_t* perm) {
+  std::memset(&d, 0, sizeof(d));
+  d.row_ptr = row_ptr;
+  d.col = col;
+  d.poff = payload_off;
+  d.payload = payload;
+  d.t_row_ptr = t_row_ptr;
+  d.t_col = t_col;
+  d.t_poff = t_payload_off;
+  d.t_payload = t_payload;
+  d.perm = perm;
+}
+
+int check_io(const mgt_desc& d, uint32_t flags, const void* row_ptr, const int32_t* col,
+             const void* payload_off, const uint8_t* payload, const void* t_row_ptr,
+             const int32_t* t_col, const void* t_payload_off, const uint8_t* t_payload,
+             const uint32_t* perm) {
+  if (!row_ptr || !payload_off || !t_row_ptr || !t_payload_off) return MGT_EINVAL;
+  if (d.nnz > 0 && (!col || !t_col)) return MGT_EINVAL;
+  if (d.payload_bytes > 0 && (!payload || !t_payload)) return MGT_EINVAL;
+  const bool want_perm = (flags & MGT_EMIT_PERM) != 0;
+  if (want_perm != (perm != nullptr)) return MGT_EINVAL;
+  return MGT_OK;
+}
+
+int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int32_t* col,
+                const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,
+                void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xc, int64_t* xb,
+                int64_t* pco, int64_t* pbo, int64_t* sd, int64_t* rd, void* ws, size_t ws_bytes,
+                int32_t* d_status, hipStream_t s) {
+  if (!p || p->batch) return MGT_EINVAL;
+  const mgt_desc& d = p->desc;
+  int st = check_io(d, p->flags, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
+                    t_payload, perm);
+  if (st != MGT_OK) return st;
+  if (partitioned && (!xc || !xb || !pco || !pbo)) return MGT_EINVAL;
+  if (!ws || ((uintptr_t)ws & 255u)) return MGT_EINVAL;
+  std::vector<HostItem> items(1);
+  HostItem& it = items[0];
+  it.d = d;
+  it.bounds = p->bounds.empty() ? nullptr : p->bounds.data();
+  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned);
+  if (!partitioned) it.d.n_parts = 1;
+  fill_outputs(it.dev, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off, t_payload,
+               perm);
+  if (partitioned) {
+    it.dev.xfer_cells = xc;
+    it.dev.xfer_bytes = xb;
+    it.dev.part_cell_off = pco;
+    it.dev.part_byte_off = pbo;
+    it.dev.sdispls = sd;
+    it.dev.rdispls = rd;
+  }
+  if (!partitioned) it.bounds = nullptr;
+  Layout y = make_layout(items);
+  if (ws_bytes < y.bytes) return MGT_ENOMEM;
+  p->timing.used = 0;
+  return run(p, items, y, ws, d_status, s);
+}
+
+size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned) {
+  std::vector<HostItem> items(1);
+  items[0].d = d;
+  if (!partitioned) items[0].d.n_parts = 1;
+  items[0].bounds = bounds;
+  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned);
+  std::memset(&items[0].dev, 0, sizeof(ItemDev));
+  return make_layout(items).bytes;
+}
+
+int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostItem>& items) {
+  if (!p || !p->batch || n < 0 || (n > 0 && !in)) return MGT_EINVAL;
+  if (n > p->lim.max_items || n > kMaxItems) return MGT_EUNSUPPORTED;
+  items.resize((size_t)n);
+  int64_t tn = 0, tc = 0, tr = 0, tp = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const mgt_item& m = in[i];
+    int st = check_desc(&m.desc, false);
+    if (st != MGT_OK) return st;
+    if (m.desc.offset_width != p->lim.offset_width) return MGT_EINVAL;
+    st = check_io(m.desc, p->flags, m.row_ptr, m.col, m.payload_off, m.payload, m.t_row_ptr, m.t_col,
+                  m.t_payload_off, m.t_payload, m.perm);
+    if (st != MGT_OK) return st;
+    const bool part = m.desc.n_parts > 1;
+    if (part && (!m.xfer_cells || !m.xfer_bytes || !m.part_cell_off || !m.part_byte_off))
+      return MGT_EINVAL;
+    tn += m.desc.nnz;
+    tc += m.desc.n_cols;
+    tr += m.desc.n_rows;
+    tp += m.desc.n_parts;
+    if (m.desc.nnz > p->lim.max_item_nnz || m.desc.n_cols > p->lim.max_item_cols) return MGT_EUNSUPPORTED;
+    HostItem& it = items[(size_t)i];
+    it.d = m.desc;
+    it.bounds = m.desc.part_bounds;
+    it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.n_parts, m.desc.part_bounds, part);
+    fill_outputs(it.dev, m.row_ptr, m.col, m.payload_off, m.payload, m.t_row_ptr, m.t_col,
+                 m.t_payload_off, m.t_payload, m.perm);
+    if (part) {
+      it.dev.xfer_cells = m.xfer_cells;
+      it.dev.xfer_bytes = m.xfer_bytes;
+      it.dev.part_cell_off = m.part_cell_off;
+      it.dev.part_byte_off = m.part_byte_off;
+    }
+  }
+  if (tn > p->lim.max_total_nnz || tc > p->lim.max_total_cols || tr > p->lim.max_total_rows ||
+      tp > p->lim.max_total_parts)
+    return MGT_EUNSUPPORTED;
+  return MGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mgt_version(void) { return "mgt 0.1.0 (gfx950)"; }
+
+int mgt_plan(const mgt_desc* desc, mgt_plan_t* out, size_t* workspace_bytes) {
+  if (!out) return MGT_EINVAL;
+  int st = check_desc(desc, false);
+  if (st != MGT_OK) return st;
+  if ((desc->flags & ~(uint32_t)(MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING)) != 0) return MGT_EINVAL;
+  mgt_plan_s* p = new (std::nothrow) mgt_plan_s();
+  if (!p) return MGT_ENOMEM;
+  p->desc = *desc;
+  p->flags = desc->flags;
+  if (desc->part_bounds) p->bounds.assign(desc->part_bounds, desc->part_bounds + desc->n_parts + 1);
+  else p->bounds = {0, desc->n_rows};
+  p->desc.part_bounds = p->bounds.data();
+  p->ws_plain = single_ws(p->desc, p->bounds.data(), false);
+  p->ws_part = single_ws(p->desc, p->bounds.data(), true);
+  *out = p;
+  if (workspace_bytes) *workspace_bytes = std::max(p->ws_plain, p->ws_part);
+  return MGT_OK;
+}
+
+int mgt_plan_destroy(mgt_plan_t p) {
+  if (!p) return MGT_EINVAL;
+  if (p->upload_pending) hipEventSynchronize(p->upload_done);
+  if (p->staging) hipHostFree(p->staging);
+  if (p->upload_done) hipEventDestroy(p->upload_done);
+  for (auto e : p->timing.ev) hipEventDestroy(e);
+  delete p;
+  return MGT_OK;
+}
+
+int mgt_transpose(mgt_plan_t plan, const void* row_ptr, const int32_t* col, const void* payload_off,
+                  const uint8_t* payload, void* t_row_ptr, int32_t* t_col, void* t_payload_off,
+                  uint8_t* t_payload, uint32_t* perm, void* workspace, size_t workspace_bytes,
+                  int32_t* d_status, hipStream_t stream) {
+  return single_call(plan, false, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
+                     t_payload, perm, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, workspace,
+                     workspace_bytes, d_status, stream);
+}
+
+int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_t* col,
+                              const void* payload_off, const uint8_t* payload, void* t_row_ptr,
+                              int32_t* t_col, void* t_payload_off, uint8_t* t_payload, uint32_t* perm,
+                              int64_t* xfer_cells, int64_t* xfer_bytes, int64_t* part_cell_off,
+                              int64_t* part_byte_off, int64_t* sdispls, int64_t* rdispls,
+                              void* workspace, size_t workspace_bytes, int32_t* d_status,
+                              hipStream_t stream) {
+  if (plan && !plan->batch && plan->desc.n_parts > 1 && plan->desc.n_rows != plan->desc.n_cols)
+    return MGT_EINVAL;
+  return single_call(plan, true, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
+                     t_payload, perm, xfer_cells, xfer_bytes, part_cell_off, part_byte_off, sdispls,
+                     rdispls, workspace, workspace_bytes, d_status, stream);
+}
+
+int mgt_batch_plan(const mgt_batch_limits* lim, mgt_plan_t* out, size_t* workspace_bytes) {
+  if (!lim || !out) return MGT_EINVAL;
+  if (lim->max_items < 1 || lim->max_items > kMaxItems) return MGT_EUNSUPPORTED;
+  if (lim->offset_width != 4 && lim->offset_width != 8) return MGT_EINVAL;
+  if (lim->max_total_nnz < 0 || lim->max_total_cols < 0 || lim->max_total_rows < 0 ||
+      lim->max_total_parts < 0 || lim->max_item_nnz < 0 || lim->max_item_cols < 0)
+    return MGT_EINVAL;
+  if ((lim->flags & ~(uint32_t)(MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING)) != 0) return MGT_EINVAL;
+  mgt_plan_s* p = new (std::nothrow) mgt_plan_s();
+  if (!p) return MGT_ENOMEM;
+  p->batch = true;
+  p->lim = *lim;
+  p->flags = lim->flags;
+  *out = p;
+  if (workspace_bytes) {
+    // Estimate for a batch at the limits; mgt_batch_workspace gives the exact
+    // size of a given batch. Level buffers dominate: 2 x (16 B per cell +
+    // payload); payload is bounded by the caller, so it is not included here.
+    const uint64_t cells = (uint64_t)lim->max_total_nnz;
+    const uint64_t segs = 2ull * (uint64_t)lim->max_total_cols + cells / 512 + (uint64_t)lim->max_items;
+    *workspace_bytes = (size_t)(2 * 16 * cells + 4 * segs * (sizeof(Seg) + 24) + 64ull * (cells / 16) +
+                                (1u << 20));
+  }
+  return MGT_OK;
+}
+
+int mgt_batch_workspace(mgt_plan_t plan, const mgt_item* items, int32_t n_items, size_t* bytes) {
+  if (!bytes) return MGT_EINVAL;
+  std::vector<HostItem> hi;
+  int st = batch_items(plan, items, n_items, hi);
+  if (st != MGT_OK) return st;
+  *bytes = n_items ? make_layout(hi).bytes : 256;
+  return MGT_OK;
+}
+
+int mgt_batch_submit(mgt_plan_t plan, const mgt_item* items, int32_t n_items, void* workspace,
+                     size_t workspace_bytes, int32_t* d_status, hipStream_t stream, hipEvent_t done) {
+  std::vector<HostItem> hi;
+  int st = batch_items(plan, items, n_items, hi);
+  if (st != MGT_OK) return st;
+  if (n_items == 0) {
+    if (done && hipEventRecord(done, stream) != hipSuccess) return MGT_EHIP;
+    return MGT_OK;
+  }
+  if (!workspace || ((uintptr_t)workspace & 255u)) return MGT_EINVAL;
+  Layout y = make_layout(hi);
+  if (workspace_bytes < y.bytes) return MGT_ENOMEM;
+  plan->timing.used = 0;
+  st = run(plan, hi, y, workspace, d_status, stream);
+  if (st != MGT_OK) return st;
+  if (done && hipEventRecord(done, stream) != hipSuccess) return MGT_EHIP;
+  return MGT_OK;
+}
+
+int mgt_plan_stage_times(mgt_plan_t plan, float* ms, const char** names, int32_t capacity,
+                         int32_t* count) {
+  if (!plan || !count) return MGT_EINVAL;
+  Timing& t = plan->timing;
+  const int n = t.used > 1 ? t.used - 1 : 0;
+  *count = n;
+  if (n == 0) return MGT_OK;
+  if (hipEventSynchronize(t.ev[t.used - 1]) != hipSuccess) return MGT_EHIP;
+  for (int i = 0; i < n && i < capacity; ++i) {
+    float v = 0.f;
+    if (hipEventElapsedTime(&v, t.ev[i], t.ev[i + 1]) != hipSuccess) return MGT_EHIP;
+    if (ms) ms[i] = v;
+    if (names) names[i] = t.names[i + 1];
+  }
+  return MGT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,295 @@
+"""Thin Python binding of libmgt (the C ABI in include/mgt.h).
+
+Argument marshalling only: every step of the transpose runs in the library's
+HIP kernels. PyTorch provides device memory and the stream. The same names as
+the C entry points are exposed (``mgt_plan``, ``mgt_transpose``,
+``mgt_transpose_partitioned``, ``mgt_batch_plan``, ``mgt_batch_workspace``,
+``mgt_batch_submit``), plus small conveniences that allocate the outputs.
+
+If libmgt.so has not been built this module raises on import: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgt.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+VALIDATE, EMIT_PERM, DEBUG_TIMING = 1, 2, 4
+_NAMES = {0: "MGT_OK", -1: "MGT_EINVAL", -2: "MGT_ERANGE", -3: "MGT_ENOMEM", -4: "MGT_EHIP",
+          -5: "MGT_EUNSUPPORTED", -6: "MGT_ECANCELED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmgt.so is not built ({LIB_PATH}); run __graft_entry__.build() or "
+                      "python -m paper_2012_06012_amd.build")
+
+
+class MgtError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        super().__init__(f"{what}: {_NAMES.get(code, code)}")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("payload_bytes", ctypes.c_int64), ("offset_width", ctypes.c_int32),
+                ("n_parts", ctypes.c_int32), ("part_bounds", ctypes.c_void_p),
+                ("flags", ctypes.c_uint32)]
+
+
+class Limits(ctypes.Structure):
+    _fields_ = [("max_items", ctypes.c_int32), ("offset_width", ctypes.c_int32),
+                ("max_total_nnz", ctypes.c_int64), ("max_total_cols", ctypes.c_int64),
+                ("max_total_rows", ctypes.c_int64), ("max_total_parts", ctypes.c_int64),
+                ("max_item_nnz", ctypes.c_int64), ("max_item_cols", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
+class Item(ctypes.Structure):
+    _fields_ = [("desc", Desc)] + [(n, ctypes.c_void_p) for n in (
+        "row_ptr", "col", "payload_off", "payload", "t_row_ptr", "t_col", "t_payload_off",
+        "t_payload", "perm", "xfer_cells", "xfer_bytes", "part_cell_off", "part_byte_off")]
+
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i32, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+_lib.mgt_plan.argtypes = [ctypes.POINTER(Desc), ctypes.POINTER(_vp), ctypes.POINTER(_sz)]
+_lib.mgt_plan_destroy.argtypes = [_vp]
+_lib.mgt_transpose.argtypes = [_vp] * 10 + [_vp, _sz, _vp, _vp]
+_lib.mgt_transpose_partitioned.argtypes = [_vp] * 16 + [_vp, _sz, _vp, _vp]
+_lib.mgt_batch_plan.argtypes = [ctypes.POINTER(Limits), ctypes.POINTER(_vp), ctypes.POINTER(_sz)]
+_lib.mgt_batch_workspace.argtypes = [_vp, ctypes.POINTER(Item), _i32, ctypes.POINTER(_sz)]
+_lib.mgt_batch_submit.argtypes = [_vp, ctypes.POINTER(Item), _i32, _vp, _sz, _vp, _vp, _vp]
+_lib.mgt_plan_stage_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_char_p), _i32, ctypes.POINTER(_i32)]
+_lib.mgt_version.restype = ctypes.c_char_p
+for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
+           "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
+            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
+            "mgt_version")
+
+
+def version() -> str:
+    return _lib.mgt_version().decode()
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return t.data_ptr() if t.numel() else None
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise MgtError(code, what)
+
+
+# ----------------------------------------------------------------------------- plans
+
+class Plan:
+    """Owns an mgt plan (host object)."""
+
+    def __init__(self, handle: int, workspace_bytes: int, desc: Optional[Desc], batch: bool,
+                 bounds: Optional[np.ndarray] = None):
+        self.handle = handle
+        self.workspace_bytes = workspace_bytes
+        self.desc = desc
+        self.batch = batch
+        self._bounds = bounds
+
+    def close(self):
+        if self.handle:
+            _lib.mgt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def stage_times(self):
+        ms = (ctypes.c_float * 64)()
+        names = (ctypes.c_char_p * 64)()
+        n = _i32(0)
+        _check(_lib.mgt_plan_stage_times(self.handle, ms, names, 64, ctypes.byref(n)), "stage_times")
+        return [(names[i].decode(), ms[i]) for i in range(min(n.value, 64))]
+
+
+def mgt_plan(n_rows: int, n_cols: int, nnz: int, payload_bytes: int, offset_width: int = 8,
+             part_bounds: Optional[Sequence[int]] = None, flags: int = 0) -> Plan:
+    b = None if part_bounds is None else np.ascontiguousarray(part_bounds, dtype=np.int64)
+    d = Desc(n_rows, n_cols, nnz, payload_bytes, offset_width,
+             1 if b is None else len(b) - 1, None if b is None else b.ctypes.data, flags)
+    h = _vp()
+    ws = _sz()
+    _check(_lib.mgt_plan(ctypes.byref(d), ctypes.byref(h), ctypes.byref(ws)), "mgt_plan")
+    return Plan(h.value, ws.value, d, False, b)
+
+
+def mgt_batch_plan(max_items: int, max_total_nnz: int, max_total_cols: int,
+                   max_total_rows: int, max_total_parts: int, max_item_nnz: int,
+                   max_item_cols: int, offset_width: int = 8, flags: int = 0) -> Plan:
+    lim = Limits(max_items, offset_width, max_total_nnz, max_total_cols, max_total_rows,
+                 max_total_parts, max_item_nnz, max_item_cols, flags)
+    h = _vp()
+    ws = _sz()
+    _check(_lib.mgt_batch_plan(ctypes.byref(lim), ctypes.byref(h), ctypes.byref(ws)),
+           "mgt_batch_plan")
+    return Plan(h.value, ws.value, None, True)
+
+
+# ----------------------------------------------------------------------------- raw entry points
+
+def mgt_transpose(plan: Plan, row_ptr, col, payload_off, payload, t_row_ptr, t_col,
+                  t_payload_off, t_payload, perm, workspace, d_status=None, stream=None) -> None:
+    _check(_lib.mgt_transpose(plan.handle, _ptr(row_ptr), _ptr(col), _ptr(payload_off),
+                              _ptr(payload), _ptr(t_row_ptr), _ptr(t_col), _ptr(t_payload_off),
+                              _ptr(t_payload), _ptr(perm), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _ptr(d_status),
+                              _stream(stream)), "mgt_transpose")
+
+
+def mgt_transpose_partitioned(plan: Plan, row_ptr, col, payload_off, payload, t_row_ptr, t_col,
+                              t_payload_off, t_payload, perm, xfer_cells, xfer_bytes,
+                              part_cell_off, part_byte_off, sdispls, rdispls, workspace,
+                              d_status=None, stream=None) -> None:
+    _check(_lib.mgt_transpose_partitioned(
+        plan.handle, _ptr(row_ptr), _ptr(col), _ptr(payload_off), _ptr(payload), _ptr(t_row_ptr),
+        _ptr(t_col), _ptr(t_payload_off), _ptr(t_payload), _ptr(perm), _ptr(xfer_cells),
+        _ptr(xfer_bytes), _ptr(part_cell_off), _ptr(part_byte_off), _ptr(sdispls), _ptr(rdispls),
+        _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(d_status),
+        _stream(stream)), "mgt_transpose_partitioned")
+
+
+def make_items(entries) -> ctypes.Array:
+    """entries: list of dicts with 'desc' (Desc) and tensor fields named as in mgt_item."""
+    arr = (Item * len(entries))()
+    for i, e in enumerate(entries):
+        arr[i].desc = e["desc"]
+        for name in ("row_ptr", "col", "payload_off", "payload", "t_row_ptr", "t_col",
+                     "t_payload_off", "t_payload", "perm", "xfer_cells", "xfer_bytes",
+                     "part_cell_off", "part_byte_off"):
+            setattr(arr[i], name, _ptr(e.get(name)))
+    return arr
+
+
+def mgt_batch_workspace(plan: Plan, items: ctypes.Array) -> int:
+    ws = _sz()
+    _check(_lib.mgt_batch_workspace(plan.handle, items, len(items), ctypes.byref(ws)),
+           "mgt_batch_workspace")
+    return ws.value
+
+
+def mgt_batch_submit(plan: Plan, items: ctypes.Array, workspace, d_status=None, stream=None,
+                     done_event=None) -> None:
+    ev = None
+    if done_event is not None:
+        ev = done_event.cuda_event if hasattr(done_event, "cuda_event") else int(done_event)
+    _check(_lib.mgt_batch_submit(plan.handle, items, len(items), _ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), _ptr(d_status),
+                                 _stream(stream), ev), "mgt_batch_submit")
+
+
+# ----------------------------------------------------------------------------- conveniences
+
+@dataclass
+class DeviceCsr:
+    """A matrix resident in device memory (torch tensors)."""
+    n_rows: int
+    n_cols: int
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    payload_off: torch.Tensor
+    payload: torch.Tensor
+    bounds: np.ndarray
+    offset_width: int
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @property
+    def payload_bytes(self) -> int:
+        return int(self.payload.numel())
+
+    @property
+    def n_parts(self) -> int:
+        return int(len(self.bounds)) - 1
+
+
+def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, device=None):
+    dev = device or a.col.device
+    odt = torch.int32 if a.offset_width == 4 else torch.int64
+    out = dict(
+        t_row_ptr=torch.empty(a.n_cols + 1, dtype=odt, device=dev),
+        t_col=torch.empty(a.nnz, dtype=torch.int32, device=dev),
+        t_payload_off=torch.empty(a.nnz + 1, dtype=odt, device=dev),
+        t_payload=torch.empty(a.payload_bytes, dtype=torch.uint8, device=dev),
+        perm=torch.empty(a.nnz, dtype=torch.int32, device=dev) if perm else None,
+    )
+    if partitioned:
+        R = a.n_parts
+        out.update(xfer_cells=torch.empty((R, R), dtype=torch.int64, device=dev),
+                   xfer_bytes=torch.empty((R, R), dtype=torch.int64, device=dev),
+                   part_cell_off=torch.empty(R + 1, dtype=torch.int64, device=dev),
+                   part_byte_off=torch.empty(R + 1, dtype=torch.int64, device=dev),
+                   sdispls=torch.empty((R, R), dtype=torch.int64, device=dev),
+                   rdispls=torch.empty((R, R), dtype=torch.int64, device=dev))
+    return out
+
+
+def plan_for(a: DeviceCsr, flags: int = 0) -> Plan:
+    return mgt_plan(a.n_rows, a.n_cols, a.nnz, a.payload_bytes, a.offset_width,
+                    a.bounds if a.n_parts >= 1 else None, flags)
+
+
+def workspace_for(plan: Plan, device) -> torch.Tensor:
+    # torch's caching allocator returns 256-byte aligned blocks
+    return torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device=device)
+
+
+def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: bool = False,
+              partitioned: bool = False, validate: bool = False, stream=None, out=None):
+    """Allocates outputs and runs mgt_transpose / mgt_transpose_partitioned.
+
+    Returns (outputs dict, status tensor). Asynchronous: read the tensors after
+    synchronising the stream.
+    """
+    flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+    if plan is None:
+        plan = plan_for(a, flags)
+    dev = a.col.device
+    if workspace is None:
+        workspace = workspace_for(plan, dev)
+    if out is None:
+        out = alloc_outputs(a, perm, partitioned, dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    if partitioned:
+        mgt_transpose_partitioned(plan, a.row_ptr, a.col, a.payload_off, a.payload,
+                                  out["t_row_ptr"], out["t_col"], out["t_payload_off"],
+                                  out["t_payload"], out["perm"], out["xfer_cells"],
+                                  out["xfer_bytes"], out["part_cell_off"], out["part_byte_off"],
+                                  out["sdispls"], out["rdispls"], workspace, status, stream)
+    else:
+        mgt_transpose(plan, a.row_ptr, a.col, a.payload_off, a.payload, out["t_row_ptr"],
+                      out["t_col"], out["t_payload_off"], out["t_payload"], out["perm"],
+                      workspace, status, stream)
+    return out, status

@@ -1,0 +1,140 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+include/mgt.h declares, and rejects bad descriptors / arguments on the host
+before anything is launched."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2012_06012_amd import mgt
+    return mgt
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "mgt.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(mgt_\w+)\(", txt, re.M)))
+
+
+def test_header_symbols_exported():
+    mgt = _lib()
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    syms = declared_symbols()
+    assert len(syms) >= 9
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) <= set(mgt.EXPORTED)
+
+
+def test_version():
+    assert "gfx950" in _lib().version()
+
+
+def test_plan_host_only_and_workspace_grows():
+    mgt = _lib()
+    p1 = mgt.mgt_plan(1000, 1000, 20000, 200000, 4, [0, 250, 500, 750, 1000])
+    p2 = mgt.mgt_plan(1 << 20, 1 << 20, 1 << 24, 1 << 28, 8, None)
+    assert 0 < p1.workspace_bytes < p2.workspace_bytes
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 10, 0, 0, 8, None), -1),                 # negative rows
+    ((10, 10, 5, 0, 3, None), -1),                 # bad offset width
+    ((10, 12, 5, 0, 8, [0, 5, 10]), -1),           # partitioned but not square
+    ((10, 10, 5, 0, 8, [0, 6, 5, 10]), -1),        # decreasing bounds
+    ((10, 10, 5, 0, 8, [1, 5, 10]), -1),           # bounds[0] != 0
+    ((10, 10, 5, 0, 8, [0, 5, 9]), -1),            # bounds[R] != n_rows
+    ((1 << 31, 10, 5, 0, 8, None), -5),            # too many rows
+    ((10, 10, 1 << 32, 0, 8, None), -5),           # nnz beyond 2^32
+    ((10, 10, 1 << 31, 0, 4, None), -5),           # int32 offsets overflow
+    ((0, 10, 5, 0, 8, None), -1),                  # cells but no rows
+])
+def test_plan_rejects(args, code):
+    mgt = _lib()
+    with pytest.raises(mgt.MgtError) as e:
+        mgt.mgt_plan(*args)
+    assert e.value.code == code
+
+
+def test_plan_rejects_too_many_parts():
+    mgt = _lib()
+    b = np.linspace(0, 5000, 1026).astype(np.int64)
+    with pytest.raises(mgt.MgtError):
+        mgt.mgt_plan(5000, 5000, 10, 0, 8, b)
+
+
+def test_transpose_rejects_null_pointers_before_launch():
+    mgt = _lib()
+    p = mgt.mgt_plan(10, 10, 5, 0, 8, None)
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    lib.mgt_transpose.argtypes = [ctypes.c_void_p] * 10 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                          ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)
+    # missing col with nnz > 0
+    rc = lib.mgt_transpose(p.handle, fake, None, fake, None, fake, fake, fake, None, None, fake,
+                           1 << 20, None, None)
+    assert rc == -1
+    # perm given without MGT_EMIT_PERM
+    rc = lib.mgt_transpose(p.handle, fake, fake, fake, None, fake, fake, fake, None, fake, fake,
+                           1 << 20, None, None)
+    assert rc == -1
+    # misaligned workspace
+    rc = lib.mgt_transpose(p.handle, fake, fake, fake, None, fake, fake, fake, None, None,
+                           ctypes.c_void_p(4097), 1 << 20, None, None)
+    assert rc == -1
+    # workspace too small
+    rc = lib.mgt_transpose(p.handle, fake, fake, fake, None, fake, fake, fake, None, None, fake,
+                           16, None, None)
+    assert rc == -3
+
+
+def test_partitioned_rejects_missing_outputs():
+    mgt = _lib()
+    p = mgt.mgt_plan(10, 10, 5, 0, 8, [0, 5, 10])
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    lib.mgt_transpose_partitioned.argtypes = [ctypes.c_void_p] * 16 + [
+        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)
+    rc = lib.mgt_transpose_partitioned(p.handle, fake, fake, fake, None, fake, fake, fake, None,
+                                       None, None, fake, fake, fake, None, None, fake, 1 << 30,
+                                       None, None)
+    assert rc == -1
+
+
+def test_batch_plan_limits_and_exact_workspace():
+    mgt = _lib()
+    with pytest.raises(mgt.MgtError):
+        mgt.mgt_batch_plan(0, 1, 1, 1, 1, 1, 1)
+    bp = mgt.mgt_batch_plan(4, 10**6, 10**5, 10**5, 64, 10**6, 10**5)
+    fake = ctypes.c_void_p(4096)
+
+    class T:  # minimal stand-in with a data_ptr for host-only sizing
+        def __init__(self, n):
+            self.n = n
+
+        def numel(self):
+            return self.n
+
+        def data_ptr(self):
+            return 4096
+
+    entries = []
+    for n, nnz in [(1000, 8000), (3000, 50000)]:
+        d = mgt.Desc(n, n, nnz, nnz * 3, 8, 1, None, 0)
+        e = dict(desc=d)
+        for k in ("row_ptr", "col", "payload_off", "payload", "t_row_ptr", "t_col",
+                  "t_payload_off", "t_payload"):
+            e[k] = T(8)
+        entries.append(e)
+    items = mgt.make_items(entries)
+    ws = mgt.mgt_batch_workspace(bp, items)
+    assert ws > (16 + 3) * 58000  # records + payload of every cell, at least once
+    # too many items for the plan
+    items5 = mgt.make_items(entries * 3)
+    with pytest.raises(mgt.MgtError):
+        mgt.mgt_batch_workspace(bp, items5)

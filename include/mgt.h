@@ -166,6 +166,8 @@ typedef struct {
   int64_t* xfer_bytes;
   int64_t* part_cell_off;
   int64_t* part_byte_off;
+  int64_t* sdispls;         /* optional (NULL): as in mgt_transpose_partitioned     */
+  int64_t* rdispls;
 } mgt_item;
 
 /* Creates a batch plan. *workspace_bytes receives an estimate for a batch at

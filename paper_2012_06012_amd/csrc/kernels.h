@@ -9,7 +9,7 @@ namespace mgt {
 
 // Geometry shared by host and device.
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
-constexpr int kSub = 1024;          // cells sorted in LDS at once
+constexpr int kSub = 2048;          // cells sorted in LDS at once
 constexpr int kScanBlock = 4096;    // elements per scan workgroup
 
 // Arguments of a partition pass (hist and scatter share them).
@@ -64,6 +64,7 @@ struct FinishArgs {
   const uint8_t* pay_in;
   const int32_t* abort_flag;
   int32_t offset_width;
+  uint64_t g8;                // grid size (multiple of 8)
 };
 
 hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,

@@ -59,7 +59,7 @@ __device__ __forceinline__ uint32_t row_of(const void* rp, int ow, uint64_t k, u
 }
 
 // Partition owning vertex v: largest p with bounds[p] <= v (0-based ranks).
-__device__ __forceinline__ uint32_t owner_of(const int64_t* lb, uint32_t R, int64_t v) {
+__device__ __forceinline__ uint32_t owner_of(const int32_t* lb, uint32_t R, int64_t v) {
   uint32_t lo = 0, hi = R;
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -73,7 +73,7 @@ __device__ __forceinline__ uint32_t owner_of(const int64_t* lb, uint32_t R, int6
 // (key - key_lo) below `shift`. Partition mode (pass 1 of a partitioned
 // matrix): the destination partition, then the top `bits` bits of the column
 // inside it. Out-of-range keys (invalid input) are clamped into the fan-out.
-__device__ __forceinline__ uint32_t digit_of(uint32_t key, const Seg& s, const int64_t* lb,
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, const Seg& s, const int32_t* lb,
                                              uint32_t R) {
   const uint32_t m = (1u << s.bits) - 1u;
   if (s.mode == 0) {
@@ -246,10 +246,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in0, uint6
 
 // ----------------------------------------------------------------------------- pass: histogram
 
+constexpr int kBatch = 8;  // independent loads in flight per lane
+
 __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   __shared__ uint32_t s_cnt[kMaxFanout];
   __shared__ uint32_t s_byt[kMaxFanout];
-  __shared__ int64_t s_lb[kMaxParts + 1];
+  __shared__ int32_t s_lb[kMaxParts + 1];
   __shared__ Seg s_seg;
   __shared__ uint32_t s_si;
   __shared__ uint64_t s_red[kNW + 1];
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   const uint32_t R = (uint32_t)it->n_parts;
   const uint32_t F = seg_fanout(sg, R);
   if (sg.mode)
-    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = it->bounds[i];
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)it->bounds[i];
   for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
     s_cnt[d] = 0;
     s_byt[d] = 0;
@@ -279,26 +281,54 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   const int ow = a.offset_width;
   uint64_t mybytes = 0;
+  constexpr uint64_t kStride = (uint64_t)kBlock * kBatch;
   if (a.pass == 0) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
     const int32_t* col = it->col;
     const void* poff = it->poff;
-    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kBlock) {
-      const uint64_t k = kbase + c;
-      const uint32_t key = (uint32_t)col[k];
-      const uint32_t sz = (uint32_t)(ld_off(poff, k + 1, ow) - ld_off(poff, k, ow));
-      const uint32_t d = digit_of(key, sg, s_lb, R);
-      atomicAdd(&s_cnt[d], 1u);
-      atomicAdd(&s_byt[d], sz);
-      mybytes += sz;
+    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+      uint32_t key[kBatch];
+      int64_t p0[kBatch], p1[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const uint64_t cc = c + (uint64_t)q * kBlock;
+        key[q] = 0; p0[q] = 0; p1[q] = 0;
+        if (cc < c_end) {
+          const uint64_t k = kbase + cc;
+          key[q] = (uint32_t)col[k];
+          p0[q] = ld_off(poff, k, ow);
+          p1[q] = ld_off(poff, k + 1, ow);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (c + (uint64_t)q * kBlock < c_end) {
+          const uint32_t sz = (uint32_t)(p1[q] - p0[q]);
+          const uint32_t d = digit_of(key[q], sg, s_lb, R);
+          atomicAdd(&s_cnt[d], 1u);
+          atomicAdd(&s_byt[d], sz);
+          mybytes += sz;
+        }
+      }
     }
   } else {
-    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kBlock) {
-      const uint2 ks = a.ks_in[sg.cell0 + c];
-      const uint32_t d = digit_of(ks.x, sg, s_lb, R);
-      atomicAdd(&s_cnt[d], 1u);
-      atomicAdd(&s_byt[d], ks.y);
-      mybytes += ks.y;
+    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+      uint2 ks[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const uint64_t cc = c + (uint64_t)q * kBlock;
+        ks[q] = make_uint2(0, 0);
+        if (cc < c_end) ks[q] = a.ks_in[sg.cell0 + cc];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (c + (uint64_t)q * kBlock < c_end) {
+          const uint32_t d = digit_of(ks[q].x, sg, s_lb, R);
+          atomicAdd(&s_cnt[d], 1u);
+          atomicAdd(&s_byt[d], ks[q].y);
+          mybytes += ks[q].y;
+        }
+      }
     }
   }
   uint64_t tot;
@@ -312,6 +342,575 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   if (threadIdx.x == 0) {
     a.ttot[tile] = (uint32_t)tot;
     if (tot >> 32) raise_status(a.item_status, a.abort_flag, it->status_index, MGT_EUNSUPPORTED);
+  }
+}
+
+// ----------------------------------------------------------------------------- shared sub-chunk sort
+
+// LDS state of one stable sub-chunk sort.
+struct SortLds {
+  uint32_t key[kSub];
+  uint32_t sz[kSub];
+  uint32_t row[kSub];
+  uint32_t idx[kSub];
+  uint32_t src[kSub];       // payload offset relative to the sub-chunk's first byte
+  uint32_t bpre[kSub + 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
+  uint16_t dig[kSub];
+  uint16_t wc[kMaxFanout * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
+};
+
+// Ranks each lane's cells stably by digit (ballot multisplit per 64-cell
+// round, counters per (digit, wave)), scans the counters digit-major and
+// stores the cells in sorted order. Registers hold kItems cells per lane in
+// wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
+__device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint32_t n,
+                                         const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
+                                         const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
+                                         const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems]) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t E = F * kNW;
+  for (uint32_t e = threadIdx.x; e < E; e += kBlock) L.wc[e] = 0;
+  __syncthreads();
+  uint32_t rank[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    const bool act = i < n;
+    const uint32_t d = act ? dg[r] : 0u;
+    const uint64_t peers = match_peers(d, act, dbits);
+    rank[r] = 0;
+    if (act) {
+      const uint32_t below = popc_below(peers);
+      const uint32_t old = L.wc[d * kNW + w];
+      if (below == 0) L.wc[d * kNW + w] = (uint16_t)(old + (uint32_t)__popcll(peers));
+      rank[r] = old + below;
+    }
+  }
+  __syncthreads();
+  {
+    const uint32_t per = (E + kBlock - 1) / kBlock;
+    const uint32_t e0 = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t e = e0; e < e0 + per && e < E; ++e) s += L.wc[e];
+    __shared__ uint32_t red[kNW + 1];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kNW>(s, red, tot);
+    for (uint32_t e = e0; e < e0 + per && e < E; ++e) {
+      const uint32_t v = L.wc[e];
+      L.wc[e] = (uint16_t)ex;
+      ex += v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    if (i < n) {
+      const uint32_t p = (uint32_t)L.wc[dg[r] * kNW + w] + rank[r];
+      L.key[p] = key[r];
+      L.sz[p] = sz[r];
+      L.row[p] = row[r];
+      L.idx[p] = idx[r];
+      L.src[p] = src[r];
+      L.dig[p] = (uint16_t)dg[r];
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int kPer = kSub / kBlock;
+    const uint32_t p0 = threadIdx.x * kPer;
+    uint32_t v[kPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      v[q] = (p0 + q < n) ? L.sz[p0 + q] : 0u;
+      s += v[q];
+    }
+    __shared__ uint32_t red2[kNW + 1];
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kNW>(s, red2, tot);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (p0 + q < n) L.bpre[p0 + q] = ex;
+      ex += v[q];
+    }
+    if (threadIdx.x == 0) L.bpre[n] = tot;
+  }
+  __syncthreads();
+}
+
+// Exclusive prefix (in cell order i = wave*kWaveCells + r*64 + lane) of the
+// per-cell sizes of a sub-chunk. Returns the sub-chunk total.
+__device__ __forceinline__ uint32_t sub_src_prefix(const uint32_t (&sz)[kItems], uint32_t (&src)[kItems],
+                                                   uint32_t* red) {
+  const uint32_t w = threadIdx.x / kWave;
+  uint32_t carry = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t inc = wave_incl_scan_u32(sz[r]) + carry;
+    src[r] = inc - sz[r];
+    carry = wave_bcast(inc, kWave - 1);
+  }
+  if (lane_id() == 0) red[w] = carry;
+  __syncthreads();
+  uint32_t wbase = 0, tot = 0;
+  for (uint32_t q = 0; q < (uint32_t)kNW; ++q) {
+    const uint32_t t = red[q];
+    if (q < w) wbase += t;
+    tot += t;
+  }
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) src[r] += wbase;
+  __syncthreads();
+  return tot;
+}
+
+// Row owning cell k of an item, found by the whole workgroup: each round
+// probes kBlock evenly spaced row offsets and keeps the last one <= k.
+__device__ __forceinline__ uint32_t coop_row_search(const void* rp, int ow, uint64_t n_rows,
+                                                    uint64_t k) {
+  uint64_t lo = 0, hi = n_rows;  // row_ptr[lo] <= k, answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint64_t step = (hi - lo + kBlock - 1) / kBlock;
+    const uint64_t p = lo + (uint64_t)threadIdx.x * step;
+    const bool ok = p < hi && (uint64_t)ld_off(rp, p, ow) <= k;
+    int c = __syncthreads_count(ok);
+    c = c < 1 ? 1 : c;
+    lo = lo + (uint64_t)(c - 1) * step;
+    hi = min(lo + step, hi);
+  }
+  return (uint32_t)lo;
+}
+
+// Rows of the cells [k0, k0 + n) of an item whose first cell lies in row r0:
+// counts the rows starting at each position (empty rows included) and scans
+// the counts, so row(k0 + i) = r0 + incl[i]. Uses `incl` (kSub entries of
+// LDS). Returns the row of cell k0 + n. Every thread must call it.
+__device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t n_rows, uint64_t k0,
+                                                uint32_t n, uint32_t r0, uint32_t* incl,
+                                                uint32_t* s_extra, uint32_t* red) {
+  for (uint32_t i = threadIdx.x; i < (uint32_t)kSub; i += kBlock) incl[i] = 0;
+  if (threadIdx.x == 0) *s_extra = 0;
+  __syncthreads();
+  const uint64_t kend = k0 + n;
+  for (uint64_t base = (uint64_t)r0 + 1;; base += kBlock) {
+    const uint64_t r = base + threadIdx.x;
+    bool stop = r >= n_rows;
+    if (!stop) {
+      const uint64_t v = (uint64_t)ld_off(rp, r, ow);
+      if (v >= k0 && v < kend) atomicAdd(&incl[v - k0], 1u);
+      else if (v == kend) atomicAdd(s_extra, 1u);
+      stop = v > kend;
+    }
+    if (__syncthreads_or(stop)) break;
+  }
+  // inclusive scan of the per-position row counts
+  constexpr int kPer = kSub / kBlock;
+  const uint32_t p0 = threadIdx.x * kPer;
+  uint32_t v[kPer];
+  uint32_t s = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = incl[p0 + q];
+    s += v[q];
+  }
+  uint32_t tot;
+  uint32_t ex = block_excl_scan<kNW>(s, red, tot);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    ex += v[q];
+    incl[p0 + q] = ex;
+  }
+  __syncthreads();
+  return r0 + tot + *s_extra;
+}
+
+// Payload copies of a lane's kItems cells. When every cell is dword aligned on
+// both sides and at most 32 bytes, all loads are issued before any store;
+// when every cell is at most 16 bytes, bytes move in two batches of four
+// cells; otherwise cell by cell.
+__device__ __forceinline__ void copy_cells(uint8_t* const (&dst)[kItems], const uint8_t* const (&src)[kItems],
+                                           const uint32_t (&sz)[kItems]) {
+  bool small_aligned = true, small = true;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    small_aligned &= sz[r] == 0u ||
+                     (sz[r] <= 32u && ((sz[r] | (uint32_t)(uintptr_t)src[r] | (uint32_t)(uintptr_t)dst[r]) & 3u) == 0);
+    small &= sz[r] <= 16u;
+  }
+  if (small_aligned) {
+    uint32_t v[kItems][8];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((uint32_t)(4 * j) < sz[r]) v[r][j] = ((const uint32_t*)src[r])[j];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((uint32_t)(4 * j) < sz[r]) ((uint32_t*)dst[r])[j] = v[r][j];
+  } else if (small) {
+#pragma unroll
+    for (int h = 0; h < kItems; h += 4) {
+      uint8_t v[4][16];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if ((uint32_t)j < sz[h + r]) v[r][j] = src[h + r][j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if ((uint32_t)j < sz[h + r]) dst[h + r][j] = v[r][j];
+    }
+  } else {
+    for (int r = 0; r < kItems; ++r)
+      if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
+  }
+}
+
+// ----------------------------------------------------------------------------- pass: scatter
+
+// Loads of one sub-chunk, kept in registers so the next sub-chunk can be in
+// flight while the current one is sorted and written.
+struct SubLoad {
+  uint32_t a[kItems], b[kItems], c[kItems], d[kItems];
+};
+
+__device__ __forceinline__ void load_sub_pass0(SubLoad& S, const ItemDev* it, uint64_t kfirst,
+                                               uint32_t n, int ow) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    S.a[r] = 0; S.b[r] = 0; S.c[r] = 0; S.d[r] = 0;
+    if (i < n) {
+      const uint64_t k = kfirst + i;
+      S.a[r] = (uint32_t)it->col[k];
+      const int64_t p0 = ld_off(it->poff, k, ow), p1 = ld_off(it->poff, k + 1, ow);
+      S.b[r] = (uint32_t)(p1 - p0);
+      S.c[r] = (uint32_t)p0;           // low and high words of the payload offset
+      S.d[r] = (uint32_t)((uint64_t)p0 >> 32);
+    }
+  }
+}
+
+__device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
+                                             uint64_t pos0, uint32_t n) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    S.a[r] = 0; S.b[r] = 0; S.c[r] = 0; S.d[r] = 0;
+    if (i < n) {
+      const uint2 x = ks[pos0 + i];
+      const uint2 y = rk[pos0 + i];
+      S.a[r] = x.x; S.b[r] = x.y; S.c[r] = y.x; S.d[r] = y.y;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
+  __shared__ SortLds L;
+  __shared__ uint32_t s_rc[kMaxFanout];  // running destination cell per digit (segment relative)
+  __shared__ uint64_t s_rb[kMaxFanout];  // running destination byte per digit
+  __shared__ int32_t s_lb[kMaxParts + 1];
+  __shared__ Seg s_seg;
+  __shared__ uint32_t s_si, s_extra;
+  __shared__ uint32_t s_red[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
+  if (tile >= a.tstart[a.nseg]) return;
+  if (threadIdx.x == 0) {
+    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
+    s_si = si;
+    s_seg = a.segs[si];
+  }
+  __syncthreads();
+  const Seg sg = s_seg;
+  const uint32_t si = s_si;
+  const ItemDev* it = &a.items[sg.item];
+  const uint32_t R = (uint32_t)it->n_parts;
+  const uint32_t F = seg_fanout(sg, R);
+  const int dbits = ceil_log2(F);
+  const int ow = a.offset_width;
+  const uint64_t j = tile - a.tstart[si];
+  const uint64_t nt = a.tstart[si + 1] - a.tstart[si];
+  const uint64_t hb = a.hstart[si];
+  const uint64_t c_begin = j * a.tile_cells;
+  const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
+  const bool pass0 = a.pass == 0;
+  const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
+  const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
+  const uint64_t seg_out = sg.cell0;  // a segment's children share its cell range
+
+  if (sg.mode)
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)it->bounds[i];
+  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+    s_rc[d] = (uint32_t)(a.ocnt[hb + (uint64_t)d * nt + j] - seg_out);
+    s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
+  }
+  uint32_t r0 = 0;
+  if (pass0) r0 = coop_row_search(it->row_ptr, ow, (uint64_t)it->n_rows, kbase + c_begin);
+  __syncthreads();
+  uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+
+  SubLoad cur, nxt;
+  {
+    const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
+    if (pass0) load_sub_pass0(cur, it, kbase + c_begin, n0, ow);
+    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0);
+  }
+  for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
+    const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
+    const uint64_t c1 = c0 + kSub;
+    if (c1 < c_end) {  // next sub-chunk's loads go out now
+      const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
+      if (pass0) load_sub_pass0(nxt, it, kbase + c1, n1, ow);
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1);
+    }
+    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
+    uint64_t sub_base;
+    uint32_t first_row = 0, last_row = 0;
+    if (pass0) {
+      const uint64_t kf = kbase + c0;
+      sub_base = (uint64_t)ld_off(it->poff, kf, ow);
+      const uint32_t r_next = expand_rows(it->row_ptr, ow, (uint64_t)it->n_rows, kf, n, r0, L.bpre,
+                                          &s_extra, s_red);
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = w * kWaveCells + r * kWave + lane;
+        key[r] = cur.a[r];
+        sz[r] = cur.b[r];
+        const uint64_t p0 = (uint64_t)cur.c[r] | ((uint64_t)cur.d[r] << 32);
+        src[r] = (uint32_t)(p0 - sub_base);
+        row[r] = i < n ? r0 + L.bpre[i] : 0u;
+        idx[r] = (uint32_t)(kf + i);
+      }
+      first_row = r0;
+      last_row = r0 + L.bpre[n - 1];
+      r0 = r_next;
+      __syncthreads();  // rows consumed before sort_sub reuses the buffer
+    } else {
+      sub_base = src_sub;
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        key[r] = cur.a[r]; sz[r] = cur.b[r]; row[r] = cur.c[r]; idx[r] = cur.d[r];
+      }
+      src_sub += sub_src_prefix(sz, src, s_red);
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      dg[r] = i < n ? digit_of(key[r], sg, s_lb, R) : 0u;
+    }
+    sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
+
+    const uint8_t* src_base = pass0 ? it->payload + sub_base : a.pay_in + sub_base;
+    bool xfer_per_cell = false;
+    uint32_t src_part = 0;
+    if (track_xfer) {
+      src_part = owner_of(s_lb, R, (int64_t)first_row);
+      xfer_per_cell = owner_of(s_lb, R, (int64_t)last_row) != src_part;
+    }
+    // write the sorted cells at their digit's running destination
+    uint8_t* pd[kItems];
+    const uint8_t* ps[kItems];
+    uint32_t pz[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = r * kBlock + threadIdx.x;
+      pz[r] = 0;
+      pd[r] = a.pay_out;
+      ps[r] = src_base;
+      if (i < n) {
+        const uint32_t d = L.dig[i];
+        const uint32_t ds = L.wc[d * kNW];
+        const uint64_t cd = seg_out + s_rc[d] + (i - ds);
+        const uint64_t bd = s_rb[d] + (L.bpre[i] - L.bpre[ds]);
+        const uint32_t csz = L.sz[i];
+        a.ks_out[cd] = make_uint2(L.key[i], csz);
+        a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+        pz[r] = csz;
+        pd[r] = a.pay_out + bd;
+        ps[r] = src_base + L.src[i];
+        if (xfer_per_cell) {
+          const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
+          const uint32_t dp = d >> sg.bits;
+          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
+          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)csz);
+        }
+      }
+    }
+    copy_cells(pd, ps, pz);
+    if (track_xfer && !xfer_per_cell) {
+      const uint32_t sub = 1u << sg.bits;
+      for (uint32_t p = threadIdx.x; p < R; p += kBlock) {
+        const uint32_t d0 = p << sg.bits, d1 = d0 + sub;
+        const uint32_t i0 = L.wc[d0 * kNW];
+        const uint32_t i1 = d1 < F ? L.wc[d1 * kNW] : n;
+        if (i1 > i0) {
+          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)src_part * R + p],
+                    (unsigned long long)(i1 - i0));
+          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)src_part * R + p],
+                    (unsigned long long)(L.bpre[i1] - L.bpre[i0]));
+        }
+      }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
+      const uint32_t i0 = L.wc[d * kNW];
+      const uint32_t i1 = d + 1 < F ? L.wc[(d + 1) * kNW] : n;
+      s_rc[d] += i1 - i0;
+      s_rb[d] += L.bpre[i1] - L.bpre[i0];
+    }
+    __syncthreads();
+    cur = nxt;
+  }
+}
+
+// ----------------------------------------------------------------------------- finish
+
+__global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
+  __shared__ SortLds L;
+  __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
+  __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
+  __shared__ uint32_t s_red[kNW + 1];
+  __shared__ uint64_t s_red64[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const uint64_t bk = xcd_tile(blockIdx.x, a.g8);
+  if (bk >= a.nbuckets) return;
+  const Seg sg = a.buckets[bk];
+  const ItemDev* it = &a.items[sg.item];
+  const int ow = a.offset_width;
+  const uint32_t nc = sg.key_hi - sg.key_lo;
+  if (nc == 0) return;
+  const int dbits = ceil_log2(nc);
+  const uint64_t out_cell0 = sg.cell0 - it->cell_base;
+  const uint64_t out_byte0 = sg.byte0 - it->byte_base;
+  const uint32_t len = sg.len;
+  const bool multi = len > (uint32_t)kSub;
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  void* t_row_ptr = it->t_row_ptr;
+
+  if (multi) {
+    for (uint32_t c = threadIdx.x; c < nc; c += kBlock) {
+      s_cc[c] = 0;
+      s_cb[c] = 0;
+    }
+    __syncthreads();
+    constexpr uint32_t kStride = kBlock * kBatch;
+    for (uint32_t c = threadIdx.x; c < len; c += kStride) {
+      uint2 ks[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        const uint32_t cc = c + q * kBlock;
+        ks[q] = make_uint2(sg.key_lo, 0);
+        if (cc < len) ks[q] = a.ks_in[sg.cell0 + cc];
+      }
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (c + q * kBlock < len) {
+          uint32_t d = ks[q].x - sg.key_lo;
+          d = d < nc ? d : nc - 1;
+          atomicAdd(&s_cc[d], 1u);
+          atomicAdd((unsigned long long*)&s_cb[d], (unsigned long long)ks[q].y);
+        }
+      }
+    }
+    __syncthreads();
+    const uint32_t per = (nc + kBlock - 1) / kBlock;
+    const uint32_t e0 = threadIdx.x * per;
+    uint32_t s = 0;
+    uint64_t sb = 0;
+    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
+      s += s_cc[e];
+      sb += s_cb[e];
+    }
+    uint32_t tot;
+    uint64_t totb;
+    uint32_t ex = block_excl_scan<kNW>(s, s_red, tot);
+    uint64_t exb = block_excl_scan<kNW>(sb, s_red64, totb);
+    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
+      const uint32_t v = s_cc[e];
+      const uint64_t vb = s_cb[e];
+      s_cc[e] = ex;
+      s_cb[e] = exb;
+      st_off(t_row_ptr, (uint64_t)sg.key_lo + e, (int64_t)(out_cell0 + ex), ow);
+      ex += v;
+      exb += vb;
+    }
+    __syncthreads();
+  }
+
+  uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
+  SubLoad cur, nxt;
+  load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len));
+  for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
+    const uint32_t n = min((uint32_t)kSub, len - c0);
+    const uint32_t c1 = c0 + kSub;
+    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      key[r] = cur.a[r]; sz[r] = cur.b[r]; row[r] = cur.c[r]; idx[r] = cur.d[r];
+      const uint32_t d = key[r] - sg.key_lo;
+      dg[r] = i < n ? (d < nc ? d : nc - 1) : 0u;
+    }
+    const uint32_t subtot = sub_src_prefix(sz, src, s_red);
+    sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
+    if (!multi) {
+      // one sub-chunk: its digit scan is the column layout of the whole bucket
+      for (uint32_t c = threadIdx.x; c < nc; c += kBlock)
+        st_off(t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kNW]), ow);
+    }
+    const uint8_t* src_base = a.pay_in + src_sub;
+    uint8_t* pd[kItems];
+    const uint8_t* ps[kItems];
+    uint32_t pz[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = r * kBlock + threadIdx.x;
+      pz[r] = 0;
+      pd[r] = it->t_payload;
+      ps[r] = src_base;
+      if (i < n) {
+        uint64_t p, b;
+        if (multi) {
+          const uint32_t d = L.dig[i];
+          const uint32_t ds = L.wc[d * kNW];
+          p = out_cell0 + s_cc[d] + (i - ds);
+          b = out_byte0 + s_cb[d] + (L.bpre[i] - L.bpre[ds]);
+        } else {
+          p = out_cell0 + i;
+          b = out_byte0 + L.bpre[i];
+        }
+        it->t_col[p] = (int32_t)L.row[i];
+        if (it->perm) it->perm[p] = L.idx[i];
+        st_off(it->t_poff, p, (int64_t)b, ow);
+        pz[r] = L.sz[i];
+        pd[r] = it->t_payload + b;
+        ps[r] = src_base + L.src[i];
+      }
+    }
+    copy_cells(pd, ps, pz);
+    __syncthreads();
+    if (multi) {
+      for (uint32_t d = threadIdx.x; d < nc; d += kBlock) {
+        const uint32_t i0 = L.wc[d * kNW];
+        const uint32_t i1 = d + 1 < nc ? L.wc[(d + 1) * kNW] : n;
+        s_cc[d] += i1 - i0;
+        s_cb[d] += L.bpre[i1] - L.bpre[i0];
+      }
+      __syncthreads();
+    }
+    src_sub += subtot;
+    cur = nxt;
+    if (len == 0) break;
   }
 }
 
@@ -373,398 +972,6 @@ __global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
       a.child_tiles[cbase + d] = tiles;
       a.child_hsize[cbase + d] = tiles << nbits;
     }
-  }
-}
-
-// ----------------------------------------------------------------------------- shared sub-chunk sort
-
-// LDS state of one stable sub-chunk sort.
-struct SortLds {
-  uint32_t key[kSub];
-  uint32_t sz[kSub];
-  uint32_t row[kSub];
-  uint32_t idx[kSub];
-  uint32_t src[kSub];       // payload offset relative to the sub-chunk's first byte
-  uint32_t bpre[kSub + 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
-  uint16_t dig[kSub];
-  uint16_t wc[kMaxFanout * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
-};
-
-// Ranks each lane's cells stably by digit (ballot multisplit per 64-cell
-// round, counters per (digit, wave)), scans the counters digit-major and
-// stores the cells in sorted order. Registers: per-lane arrays of kItems cells
-// in wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
-__device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint32_t n,
-                                         const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
-                                         const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
-                                         const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems]) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t E = F * kNW;
-  for (uint32_t e = threadIdx.x; e < E; e += kBlock) L.wc[e] = 0;
-  __syncthreads();
-  uint32_t rank[kItems];
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = w * kWaveCells + r * kWave + lane;
-    const bool act = i < n;
-    const uint32_t d = act ? dg[r] : 0u;
-    const uint64_t peers = match_peers(d, act, dbits);
-    rank[r] = 0;
-    if (act) {
-      const uint32_t below = popc_below(peers);
-      const uint32_t old = L.wc[d * kNW + w];
-      if (below == 0) L.wc[d * kNW + w] = (uint16_t)(old + (uint32_t)__popcll(peers));
-      rank[r] = old + below;
-    }
-  }
-  __syncthreads();
-  // digit-major exclusive scan of the (digit, wave) counters
-  {
-    const uint32_t per = (E + kBlock - 1) / kBlock;
-    const uint32_t e0 = threadIdx.x * per;
-    uint32_t s = 0;
-    for (uint32_t e = e0; e < e0 + per && e < E; ++e) s += L.wc[e];
-    __shared__ uint32_t red[kNW + 1];
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kNW>(s, red, tot);
-    for (uint32_t e = e0; e < e0 + per && e < E; ++e) {
-      const uint32_t v = L.wc[e];
-      L.wc[e] = (uint16_t)ex;
-      ex += v;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = w * kWaveCells + r * kWave + lane;
-    if (i < n) {
-      const uint32_t p = (uint32_t)L.wc[dg[r] * kNW + w] + rank[r];
-      L.key[p] = key[r];
-      L.sz[p] = sz[r];
-      L.row[p] = row[r];
-      L.idx[p] = idx[r];
-      L.src[p] = src[r];
-      L.dig[p] = (uint16_t)dg[r];
-    }
-  }
-  __syncthreads();
-  // sizes in sorted order -> exclusive byte prefix
-  {
-    constexpr int kPer = kSub / kBlock;
-    const uint32_t p0 = threadIdx.x * kPer;
-    uint32_t v[kPer];
-    uint32_t s = 0;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      v[q] = (p0 + q < n) ? L.sz[p0 + q] : 0u;
-      s += v[q];
-    }
-    __shared__ uint32_t red2[kNW + 1];
-    uint32_t tot;
-    uint32_t ex = block_excl_scan<kNW>(s, red2, tot);
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      if (p0 + q < n) L.bpre[p0 + q] = ex;
-      ex += v[q];
-    }
-    if (threadIdx.x == 0) L.bpre[n] = tot;
-  }
-  __syncthreads();
-}
-
-// Exclusive prefix (in cell order i = wave*kWaveCells + r*64 + lane) of the
-// per-cell sizes of a sub-chunk. Returns the sub-chunk total.
-__device__ __forceinline__ uint32_t sub_src_prefix(const uint32_t (&sz)[kItems], uint32_t (&src)[kItems],
-                                                   uint32_t* red) {
-  const uint32_t w = threadIdx.x / kWave;
-  uint32_t carry = 0;
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t inc = wave_incl_scan_u32(sz[r]) + carry;
-    src[r] = inc - sz[r];
-    carry = wave_bcast(inc, kWave - 1);
-  }
-  if (lane_id() == 0) red[w] = carry;
-  __syncthreads();
-  uint32_t wbase = 0, tot = 0;
-  for (uint32_t q = 0; q < (uint32_t)kNW; ++q) {
-    const uint32_t t = red[q];
-    if (q < w) wbase += t;
-    tot += t;
-  }
-#pragma unroll
-  for (int r = 0; r < kItems; ++r) src[r] += wbase;
-  __syncthreads();
-  return tot;
-}
-
-// ----------------------------------------------------------------------------- pass: scatter
-
-__global__ __launch_bounds__(kBlock) void k_pass_scatter(PassArgs a) {
-  __shared__ SortLds L;
-  __shared__ uint64_t s_rc[kMaxFanout];  // running destination cell per digit
-  __shared__ uint64_t s_rb[kMaxFanout];  // running destination byte per digit
-  __shared__ int64_t s_lb[kMaxParts + 1];
-  __shared__ Seg s_seg;
-  __shared__ uint32_t s_si, s_rlo, s_rhi, s_first_row, s_last_row;
-  __shared__ uint32_t s_red[kNW + 1];
-  if (aborted(a.abort_flag)) return;
-  const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
-  if (tile >= a.tstart[a.nseg]) return;
-  if (threadIdx.x == 0) {
-    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
-    s_si = si;
-    s_seg = a.segs[si];
-  }
-  __syncthreads();
-  const Seg sg = s_seg;
-  const uint32_t si = s_si;
-  const ItemDev* it = &a.items[sg.item];
-  const uint32_t R = (uint32_t)it->n_parts;
-  const uint32_t F = seg_fanout(sg, R);
-  const int dbits = ceil_log2(F);
-  const int ow = a.offset_width;
-  const uint64_t j = tile - a.tstart[si];
-  const uint64_t nt = a.tstart[si + 1] - a.tstart[si];
-  const uint64_t hb = a.hstart[si];
-  const uint64_t c_begin = j * a.tile_cells;
-  const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
-  const bool pass0 = a.pass == 0;
-  const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
-  const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
-
-  if (sg.mode)
-    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = it->bounds[i];
-  for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
-    s_rc[d] = a.ocnt[hb + (uint64_t)d * nt + j];
-    s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
-  }
-  if (pass0 && threadIdx.x < 2) {
-    const uint64_t k = kbase + (threadIdx.x == 0 ? c_begin : c_end - 1);
-    const uint32_t r = row_of(it->row_ptr, ow, k, 0u, (uint32_t)(it->n_rows - 1));
-    if (threadIdx.x == 0) s_rlo = r;
-    else s_rhi = r;
-  }
-  __syncthreads();
-  const uint32_t rlo = pass0 ? s_rlo : 0u, rhi = pass0 ? s_rhi : 0u;
-  // byte offset (source side) of the current sub-chunk's first cell
-  uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-
-  for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
-    const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
-    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
-    uint64_t sub_base;
-    if (pass0) {
-      sub_base = (uint64_t)ld_off(it->poff, kbase + c0, ow);
-#pragma unroll
-      for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = w * kWaveCells + r * kWave + lane;
-        key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; src[r] = 0; dg[r] = 0;
-        if (i < n) {
-          const uint64_t k = kbase + c0 + i;
-          key[r] = (uint32_t)it->col[k];
-          const int64_t p0 = ld_off(it->poff, k, ow);
-          sz[r] = (uint32_t)(ld_off(it->poff, k + 1, ow) - p0);
-          src[r] = (uint32_t)((uint64_t)p0 - sub_base);
-          row[r] = row_of(it->row_ptr, ow, k, rlo, rhi);
-          idx[r] = (uint32_t)k;
-        }
-      }
-    } else {
-      sub_base = src_sub;
-#pragma unroll
-      for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = w * kWaveCells + r * kWave + lane;
-        key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; dg[r] = 0;
-        if (i < n) {
-          const uint2 ks = a.ks_in[sg.cell0 + c0 + i];
-          const uint2 rk = a.rk_in[sg.cell0 + c0 + i];
-          key[r] = ks.x; sz[r] = ks.y; row[r] = rk.x; idx[r] = rk.y;
-        }
-      }
-      const uint32_t tot = sub_src_prefix(sz, src, s_red);
-      src_sub += tot;
-    }
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = w * kWaveCells + r * kWave + lane;
-      if (i < n) dg[r] = digit_of(key[r], sg, s_lb, R);
-      if (track_xfer && i == 0) s_first_row = row[r];
-      if (track_xfer && i == n - 1) s_last_row = row[r];
-    }
-    sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
-
-    const uint8_t* src_base = pass0 ? it->payload + sub_base : a.pay_in + sub_base;
-    bool xfer_per_cell = false;
-    uint32_t src_part = 0;
-    if (track_xfer) {
-      src_part = owner_of(s_lb, R, (int64_t)s_first_row);
-      xfer_per_cell = owner_of(s_lb, R, (int64_t)s_last_row) != src_part;
-    }
-    // write the sorted cells at their digit's running destination
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = r * kBlock + threadIdx.x;
-      if (i < n) {
-        const uint32_t d = L.dig[i];
-        const uint32_t ds = L.wc[d * kNW];
-        const uint64_t cd = s_rc[d] + (i - ds);
-        const uint64_t bd = s_rb[d] + (L.bpre[i] - L.bpre[ds]);
-        const uint32_t csz = L.sz[i];
-        a.ks_out[cd] = make_uint2(L.key[i], csz);
-        a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
-        if (csz) copy_bytes(a.pay_out + bd, src_base + L.src[i], csz);
-        if (xfer_per_cell) {
-          const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
-          const uint32_t dp = d >> sg.bits;
-          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
-          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)csz);
-        }
-      }
-    }
-    if (track_xfer && !xfer_per_cell) {
-      const uint32_t sub = 1u << sg.bits;
-      for (uint32_t p = threadIdx.x; p < R; p += kBlock) {
-        const uint32_t d0 = p << sg.bits, d1 = d0 + sub;
-        const uint32_t i0 = L.wc[d0 * kNW];
-        const uint32_t i1 = d1 < F ? L.wc[d1 * kNW] : n;
-        if (i1 > i0) {
-          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)src_part * R + p],
-                    (unsigned long long)(i1 - i0));
-          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)src_part * R + p],
-                    (unsigned long long)(L.bpre[i1] - L.bpre[i0]));
-        }
-      }
-    }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
-      const uint32_t i0 = L.wc[d * kNW];
-      const uint32_t i1 = d + 1 < F ? L.wc[(d + 1) * kNW] : n;
-      s_rc[d] += i1 - i0;
-      s_rb[d] += L.bpre[i1] - L.bpre[i0];
-    }
-    __syncthreads();
-  }
-}
-
-// ----------------------------------------------------------------------------- finish
-
-__global__ __launch_bounds__(kBlock) void k_finish(FinishArgs a) {
-  __shared__ SortLds L;
-  __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
-  __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
-  __shared__ uint32_t s_red[kNW + 1];
-  __shared__ uint64_t s_red64[kNW + 1];
-  if (aborted(a.abort_flag)) return;
-  const Seg sg = a.buckets[blockIdx.x];
-  const ItemDev* it = &a.items[sg.item];
-  const int ow = a.offset_width;
-  const uint32_t nc = sg.key_hi - sg.key_lo;
-  if (nc == 0) return;
-  const int dbits = ceil_log2(nc);
-  const uint64_t out_cell0 = sg.cell0 - it->cell_base;
-  const uint64_t out_byte0 = sg.byte0 - it->byte_base;
-  const uint32_t len = sg.len;
-  const bool multi = len > (uint32_t)kSub;
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-  void* t_row_ptr = it->t_row_ptr;
-
-  if (multi) {
-    for (uint32_t c = threadIdx.x; c < nc; c += kBlock) {
-      s_cc[c] = 0;
-      s_cb[c] = 0;
-    }
-    __syncthreads();
-    for (uint32_t c = threadIdx.x; c < len; c += kBlock) {
-      const uint2 ks = a.ks_in[sg.cell0 + c];
-      uint32_t d = ks.x - sg.key_lo;
-      d = d < nc ? d : nc - 1;
-      atomicAdd(&s_cc[d], 1u);
-      atomicAdd((unsigned long long*)&s_cb[d], (unsigned long long)ks.y);
-    }
-    __syncthreads();
-    const uint32_t per = (nc + kBlock - 1) / kBlock;
-    const uint32_t e0 = threadIdx.x * per;
-    uint32_t s = 0;
-    uint64_t sb = 0;
-    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
-      s += s_cc[e];
-      sb += s_cb[e];
-    }
-    uint32_t tot;
-    uint64_t totb;
-    uint32_t ex = block_excl_scan<kNW>(s, s_red, tot);
-    uint64_t exb = block_excl_scan<kNW>(sb, s_red64, totb);
-    for (uint32_t e = e0; e < e0 + per && e < nc; ++e) {
-      const uint32_t v = s_cc[e];
-      const uint64_t vb = s_cb[e];
-      s_cc[e] = ex;
-      s_cb[e] = exb;
-      st_off(t_row_ptr, (uint64_t)sg.key_lo + e, (int64_t)(out_cell0 + ex), ow);
-      ex += v;
-      exb += vb;
-    }
-    __syncthreads();
-  }
-
-  uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
-  for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
-    const uint32_t n = min((uint32_t)kSub, len - c0);
-    uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = w * kWaveCells + r * kWave + lane;
-      key[r] = 0; sz[r] = 0; row[r] = 0; idx[r] = 0; dg[r] = 0;
-      if (i < n) {
-        const uint2 ks = a.ks_in[sg.cell0 + c0 + i];
-        const uint2 rk = a.rk_in[sg.cell0 + c0 + i];
-        key[r] = ks.x; sz[r] = ks.y; row[r] = rk.x; idx[r] = rk.y;
-        const uint32_t d = ks.x - sg.key_lo;
-        dg[r] = d < nc ? d : nc - 1;
-      }
-    }
-    const uint32_t subtot = sub_src_prefix(sz, src, s_red);
-    sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
-    if (!multi) {
-      // one sub-chunk: its digit scan is the column layout of the whole bucket
-      for (uint32_t c = threadIdx.x; c < nc; c += kBlock)
-        st_off(t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kNW]), ow);
-    }
-    const uint8_t* src_base = a.pay_in + src_sub;
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = r * kBlock + threadIdx.x;
-      if (i < n) {
-        uint64_t p, b;
-        if (multi) {
-          const uint32_t d = L.dig[i];
-          const uint32_t ds = L.wc[d * kNW];
-          p = out_cell0 + s_cc[d] + (i - ds);
-          b = out_byte0 + s_cb[d] + (L.bpre[i] - L.bpre[ds]);
-        } else {
-          p = out_cell0 + i;
-          b = out_byte0 + L.bpre[i];
-        }
-        it->t_col[p] = (int32_t)L.row[i];
-        if (it->perm) it->perm[p] = L.idx[i];
-        st_off(it->t_poff, p, (int64_t)b, ow);
-        const uint32_t csz = L.sz[i];
-        if (csz) copy_bytes(it->t_payload + b, src_base + L.src[i], csz);
-      }
-    }
-    __syncthreads();
-    if (multi) {
-      for (uint32_t d = threadIdx.x; d < nc; d += kBlock) {
-        const uint32_t i0 = L.wc[d * kNW];
-        const uint32_t i1 = d + 1 < nc ? L.wc[(d + 1) * kNW] : n;
-        s_cc[d] += i1 - i0;
-        s_cb[d] += L.bpre[i1] - L.bpre[i0];
-      }
-      __syncthreads();
-    }
-    src_sub += subtot;
-    if (len == 0) break;
   }
 }
 
@@ -878,7 +1085,7 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
-  if (a.nbuckets) hipLaunchKernelGGL(k_finish, grid1(a.nbuckets), dim3(kBlock), 0, s, a);
+  if (a.nbuckets) hipLaunchKernelGGL(k_finish, grid1(a.g8), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

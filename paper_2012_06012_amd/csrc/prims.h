@@ -95,21 +95,67 @@ __device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t g8) {
   return (b & 7u) * (g8 >> 3) + (b >> 3);
 }
 
-// Bytewise copy for payloads of any width and alignment; 4-byte words in the
-// middle when source and destination share their alignment modulo 4.
-__device__ __forceinline__ void copy_bytes(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src,
-                                           uint32_t n) {
+// Copies one cell's payload (any width, any alignment). Every chunk issues
+// all of its loads before its stores, so a lane waits for memory once per
+// chunk instead of once per word. Source and destination sharing their
+// alignment modulo 4 move as 4-byte words (up to 8 per chunk); otherwise as
+// bytes (up to 16 per chunk).
+__device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src,
+                                          uint32_t n) {
   if ((((uintptr_t)dst ^ (uintptr_t)src) & 3u) == 0) {
-    while (n && ((uintptr_t)dst & 3u)) { *dst++ = *src++; --n; }
-    uint32_t* d4 = (uint32_t*)dst;
+    uint32_t h = (4u - ((uintptr_t)dst & 3u)) & 3u;
+    h = h < n ? h : n;
+    uint8_t hb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if ((uint32_t)j < h) hb[j] = src[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if ((uint32_t)j < h) dst[j] = hb[j];
+    dst += h;
+    src += h;
+    n -= h;
     const uint32_t* s4 = (const uint32_t*)src;
+    uint32_t* d4 = (uint32_t*)dst;
     uint32_t w = n >> 2;
-    for (uint32_t i = 0; i < w; ++i) d4[i] = s4[i];
-    dst += 4 * w;
-    src += 4 * w;
-    n &= 3u;
+    while (w) {
+      const uint32_t m = w < 8u ? w : 8u;
+      uint32_t v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((uint32_t)j < m) v[j] = s4[j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((uint32_t)j < m) d4[j] = v[j];
+      s4 += m;
+      d4 += m;
+      w -= m;
+    }
+    const uint32_t t = n & 3u;
+    const uint8_t* sb = (const uint8_t*)s4;
+    uint8_t* db = (uint8_t*)d4;
+    uint8_t tb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if ((uint32_t)j < t) tb[j] = sb[j];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if ((uint32_t)j < t) db[j] = tb[j];
+  } else {
+    while (n) {
+      const uint32_t m = n < 16u ? n : 16u;
+      uint8_t v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if ((uint32_t)j < m) v[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j)
+        if ((uint32_t)j < m) dst[j] = v[j];
+      src += m;
+      dst += m;
+      n -= m;
+    }
   }
-  for (uint32_t i = 0; i < n; ++i) dst[i] = src[i];
 }
 
 }  // namespace mgt

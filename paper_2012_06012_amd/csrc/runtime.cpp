@@ -18,7 +18,7 @@ using namespace mgt;
 namespace {
 
 constexpr uint32_t kTileCells = 16384;    // cells per partition-pass tile (multiple of kSub)
-constexpr int kMaxBitsPerPass = 9;        // fan-out 512 per bits-mode pass
+constexpr int kMaxBitsPerPass = 8;        // fan-out 256 per bits-mode pass
 constexpr uint32_t kMaxPartFanout = 512;  // preferred fan-out of the partition pass
 constexpr int kMaxItems = 65535;
 static_assert(kTileCells % kSub == 0, "tile geometry");
@@ -423,6 +423,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.pay_in = (const uint8_t*)(W + y.o_pay[bl]);
   f.abort_flag = d_abort;
   f.offset_width = ow;
+  f.g8 = align_up(y.nseg[L], 8);
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
   MGT_HIP(launch_tails(d_items, n, d_abort, ow, s));
@@ -454,7 +455,8 @@ int check_io(const mgt_desc& d, uint32_t flags, const void* row_ptr, const int32
   if (d.nnz > 0 && (!col || !t_col)) return MGT_EINVAL;
   if (d.payload_bytes > 0 && (!payload || !t_payload)) return MGT_EINVAL;
   const bool want_perm = (flags & MGT_EMIT_PERM) != 0;
-  if (want_perm != (perm != nullptr)) return MGT_EINVAL;
+  if (!want_perm && perm) return MGT_EINVAL;
+  if (want_perm && !perm && d.nnz > 0) return MGT_EINVAL;
   return MGT_OK;
 }
 
@@ -535,6 +537,8 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
       it.dev.xfer_bytes = m.xfer_bytes;
       it.dev.part_cell_off = m.part_cell_off;
       it.dev.part_byte_off = m.part_byte_off;
+      it.dev.sdispls = m.sdispls;
+      it.dev.rdispls = m.rdispls;
     }
   }
   if (tn > p->lim.max_total_nnz || tc > p->lim.max_total_cols || tr > p->lim.max_total_rows ||

@@ -56,7 +56,8 @@ class Limits(ctypes.Structure):
 class Item(ctypes.Structure):
     _fields_ = [("desc", Desc)] + [(n, ctypes.c_void_p) for n in (
         "row_ptr", "col", "payload_off", "payload", "t_row_ptr", "t_col", "t_payload_off",
-        "t_payload", "perm", "xfer_cells", "xfer_bytes", "part_cell_off", "part_byte_off")]
+        "t_payload", "perm", "xfer_cells", "xfer_bytes", "part_cell_off", "part_byte_off",
+        "sdispls", "rdispls")]
 
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -186,7 +187,7 @@ def make_items(entries) -> ctypes.Array:
         arr[i].desc = e["desc"]
         for name in ("row_ptr", "col", "payload_off", "payload", "t_row_ptr", "t_col",
                      "t_payload_off", "t_payload", "perm", "xfer_cells", "xfer_bytes",
-                     "part_cell_off", "part_byte_off"):
+                     "part_cell_off", "part_byte_off", "sdispls", "rdispls"):
             setattr(arr[i], name, _ptr(e.get(name)))
     return arr
 
@@ -293,3 +294,47 @@ def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: b
                       out["t_col"], out["t_payload_off"], out["t_payload"], out["perm"],
                       workspace, status, stream)
     return out, status
+
+
+def batch_entries(mats: Sequence[DeviceCsr], outs: Sequence[dict], perm: bool = False,
+                  flags: int = 0):
+    """Item table entries for mgt_batch_submit (items with R > 1 are partitioned)."""
+    entries = []
+    keep = []
+    for a, o in zip(mats, outs):
+        b = np.ascontiguousarray(a.bounds, dtype=np.int64)
+        keep.append(b)
+        d = Desc(a.n_rows, a.n_cols, a.nnz, a.payload_bytes, a.offset_width, a.n_parts,
+                 b.ctypes.data, flags)
+        e = dict(desc=d, row_ptr=a.row_ptr, col=a.col, payload_off=a.payload_off,
+                 payload=a.payload, **{k: o.get(k) for k in (
+                     "t_row_ptr", "t_col", "t_payload_off", "t_payload", "perm", "xfer_cells",
+                     "xfer_bytes", "part_cell_off", "part_byte_off", "sdispls", "rdispls")})
+        entries.append(e)
+    return entries, keep
+
+
+def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm: bool = False,
+                    validate: bool = False, stream=None, outs=None, workspace=None,
+                    done_event=None):
+    """Transposes every matrix of `mats` with one mgt_batch_submit call.
+
+    Returns (outputs per item, per-item status tensor, plan, workspace)."""
+    flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+    dev = mats[0].col.device
+    if outs is None:
+        outs = [alloc_outputs(a, perm, a.n_parts > 1, dev) for a in mats]
+    if plan is None:
+        plan = mgt_batch_plan(len(mats), sum(a.nnz for a in mats), sum(a.n_cols for a in mats),
+                              sum(a.n_rows for a in mats), sum(a.n_parts for a in mats),
+                              max(a.nnz for a in mats), max(a.n_cols for a in mats),
+                              mats[0].offset_width, flags)
+    entries, keep = batch_entries(mats, outs, perm, flags)
+    items = make_items(entries)
+    need = mgt_batch_workspace(plan, items)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    status = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+    mgt_batch_submit(plan, items, workspace, status, stream, done_event)
+    del keep
+    return outs, status, plan, workspace

@@ -66,6 +66,108 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_each_way": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
 
 
+def _device(a, dev):
+    import torch
+    from paper_2012_06012_amd import mgt
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
+    return mgt.DeviceCsr(a.n_rows, a.n_cols, t(a.row_ptr), t(a.col), t(a.payload_off),
+                         t(a.payload), a.bounds, a.offset_width)
+
+
+def bench_batch(args):
+    """Many independent matrices: one mgt_batch_submit versus one mgt_transpose
+    per matrix on one stream (same matrices, bit-exact outputs compared)."""
+    import torch
+    from workloads import gen
+    from paper_2012_06012_amd import mgt
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    host = [gen.batch_item(args.seed, i, 1e3, 1e5) for i in range(args.items)]
+    mats = [_device(a, dev) for a in host]
+    cells = sum(a.nnz for a in host)
+    log(f"[batch] {len(host)} matrices, {cells} cells, generated in {time.time() - t0:.1f}s")
+    outs, status, plan, ws = mgt.batch_transpose(mats)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        mgt.batch_transpose(mats, plan=plan, workspace=ws, outs=outs)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_batch = ev0.elapsed_time(ev1) / args.steps
+    plans = [mgt.plan_for(a) for a in mats]
+    wsz = max(p.workspace_bytes for p in plans)
+    ws1 = torch.empty(wsz, dtype=torch.uint8, device=dev)
+    outs1 = [mgt.alloc_outputs(a) for a in mats]
+    for a, p, o in zip(mats, plans, outs1):
+        mgt.transpose(a, plan=p, workspace=ws1, out=o)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        for a, p, o in zip(mats, plans, outs1):
+            mgt.transpose(a, plan=p, workspace=ws1, out=o)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_plain = ev0.elapsed_time(ev1) / args.steps
+    same = all(torch.equal(o1[k], o2[k]) for o1, o2 in zip(outs, outs1) for k in o1
+               if o1[k] is not None)
+    res = {"metric": "cells/s, batched vs per-matrix plain launches", "mode": "batch",
+           "matrices": len(host), "cells": cells, "ms_batched": ms_batch, "ms_per_matrix_plain": ms_plain,
+           "cells_per_s_batched": cells / (ms_batch * 1e-3),
+           "cells_per_s_plain": cells / (ms_plain * 1e-3), "speedup": ms_plain / ms_batch,
+           "bit_exact_batched_vs_plain": bool(same),
+           "config": {"workload": "batch of matrices, n log-uniform 1e3-1e5, mean degree U{8..64}, "
+                                  "payload U{0..16} bytes per matrix", "seed": args.seed}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_serve(args):
+    """Served requests: Poisson arrivals into the continuous-batching loop,
+    then the same stream through per-request plain launches."""
+    import torch
+    from workloads import gen
+    from paper_2012_06012_amd import serve
+    from paper_2012_06012_amd.serve import Request, Server
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool_n = 32
+    host = []
+    for i in range(pool_n):
+        cells, n, deg, width, r = gen.served_request_params(args.seed, i, 1e4, 1e7)
+        host.append(gen.generate(n, n, seed=(args.seed << 24) + i + 11, deg_law=gen.DEG_POISSON,
+                                 deg_mean=float(deg), pay_law=gen.PAY_BYTES, w_lo=width,
+                                 w_hi=width, offset_width=8, bounds=gen.equal_bounds(n, min(r, n))))
+    pool = [_device(a, dev) for a in host]
+    log(f"[serve] pool of {pool_n} inputs, {sum(a.nnz for a in host)} cells, "
+        f"{time.time() - t0:.1f}s")
+    n_req = args.items
+
+    def make(rate):
+        arr = gen.poisson_arrivals(n_req, rate, args.seed + 3)
+        return [Request(rid=i, mat=pool[i % pool_n], arrival=t, partitioned=pool[i % pool_n].n_parts > 1)
+                for i, t in enumerate(arr)]
+
+    budget = 200 << 30
+    # capacity of the plain path: back-to-back, no arrivals gaps
+    plain = Server(serve.PlainExecutor(), budget, max_batch=1, n_slots=1)
+    st = plain.run([Request(rid=i, mat=pool[i % pool_n], arrival=0.0,
+                            partitioned=pool[i % pool_n].n_parts > 1) for i in range(64)])
+    mu = 64 / st.last_done
+    log(f"[serve] plain capacity {mu:.1f} req/s")
+    out = {}
+    for frac in (0.7, 1.2):
+        rate = frac * mu
+        sb = Server(serve.GpuExecutor(n_slots=2, max_items=64), budget, max_batch=32, n_slots=2).run(make(rate))
+        sp = Server(serve.PlainExecutor(), budget, max_batch=1, n_slots=1).run(make(rate))
+        out[f"{frac}mu"] = {"batched": sb.summary(), "plain": sp.summary()}
+        log(f"[serve] rate {rate:.1f}/s: batched {sb.summary()} plain {sp.summary()}")
+    res = {"metric": "served p50/p99 latency and sustained cells/s, batched vs plain",
+           "mode": "serve", "requests": n_req, "plain_capacity_req_s": mu, "results": out,
+           "config": {"workload": "requests of log-uniform 1e4-1e7 cells, widths U{0..32}, "
+                                  "R U{1..64}, Poisson arrivals", "budget_bytes": budget}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,9 +182,18 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this size (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters and measures copy bandwidth)")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain",
+                    help="plain: the headline line; batch: many matrices in one mgt_batch_submit "
+                         "vs per-matrix launches; serve: the continuous-batching request loop vs "
+                         "per-request plain launches")
+    ap.add_argument("--items", type=int, default=512, help="batch / serve: matrices or requests")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
               "multi-GPU path; see DESIGN.md for how the transpose would shard.", file=sys.stderr)

@@ -37,6 +37,7 @@ struct PassArgs {
   uint64_t g8;                // grid size (multiple of 8)
   uint32_t tile_cells;        // multiple of kSub
   int32_t offset_width;
+  int32_t with_idx;           // records carry the input cell index (for perm)
 };
 
 struct ChildArgs {
@@ -64,6 +65,7 @@ struct FinishArgs {
   const uint8_t* pay_in;
   const int32_t* abort_flag;
   int32_t offset_width;
+  int32_t with_idx;
   uint64_t g8;                // grid size (multiple of 8)
 };
 

@@ -35,13 +35,20 @@ __device__ __forceinline__ uint32_t seg_fanout(const Seg& s, uint32_t R) {
   return s.mode ? (R << s.bits) : (1u << s.bits);
 }
 
-// Largest s with tstart[s] <= t (the segment that owns tile t).
-__device__ __forceinline__ uint32_t find_seg(const uint64_t* tstart, uint32_t nseg, uint64_t t) {
-  uint32_t lo = 0, hi = nseg;
+// Largest s with tstart[s] <= t (the segment that owns tile t), found by the
+// whole workgroup: each round probes kBlock evenly spaced segments and keeps
+// the last one <= t, so 2^16 segments take two dependent loads, not sixteen.
+// Every thread must call it; all get the same answer.
+__device__ __forceinline__ uint32_t coop_find_seg(const uint64_t* tstart, uint32_t nseg, uint64_t t) {
+  uint32_t lo = 0, hi = nseg;  // tstart[lo] <= t, answer in [lo, hi)
   while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (tstart[mid] <= t) lo = mid;
-    else hi = mid;
+    const uint32_t step = (hi - lo + kBlock - 1) / kBlock;
+    const uint32_t p = lo + threadIdx.x * step;
+    const bool ok = p < hi && tstart[p] <= t;
+    int c = __syncthreads_count(ok);
+    c = c < 1 ? 1 : c;
+    lo = lo + (uint32_t)(c - 1) * step;
+    hi = min(lo + step, hi);
   }
   return lo;
 }
@@ -258,10 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   if (aborted(a.abort_flag)) return;
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
-  if (threadIdx.x == 0) {
-    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
-    s_si = si;
-    s_seg = a.segs[si];
+  {
+    const uint32_t si = coop_find_seg(a.tstart, a.nseg, tile);
+    if (threadIdx.x == 0) {
+      s_si = si;
+      s_seg = a.segs[si];
+    }
   }
   __syncthreads();
   const Seg sg = s_seg;
@@ -486,8 +495,15 @@ __device__ __forceinline__ uint32_t coop_row_search(const void* rp, int ow, uint
 // counts the rows starting at each position (empty rows included) and scans
 // the counts, so row(k0 + i) = r0 + incl[i]. Uses `incl` (kSub entries of
 // LDS). Returns the row of cell k0 + n. Every thread must call it.
+// `pf` is row_ptr[r0 + 1 + threadIdx.x] (or ~0 past the last row), loaded
+// ahead of time by the caller so the first batch does not wait for memory.
+__device__ __forceinline__ uint64_t prefetch_row(const void* rp, int ow, uint64_t n_rows, uint32_t r0) {
+  const uint64_t r = (uint64_t)r0 + 1 + threadIdx.x;
+  return r < n_rows ? (uint64_t)ld_off(rp, r, ow) : ~0ull;
+}
+
 __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t n_rows, uint64_t k0,
-                                                uint32_t n, uint32_t r0, uint32_t* incl,
+                                                uint32_t n, uint32_t r0, uint64_t pf, uint32_t* incl,
                                                 uint32_t* s_extra, uint32_t* red) {
   for (uint32_t i = threadIdx.x; i < (uint32_t)kSub; i += kBlock) incl[i] = 0;
   if (threadIdx.x == 0) *s_extra = 0;
@@ -497,7 +513,7 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
     const uint64_t r = base + threadIdx.x;
     bool stop = r >= n_rows;
     if (!stop) {
-      const uint64_t v = (uint64_t)ld_off(rp, r, ow);
+      const uint64_t v = base == (uint64_t)r0 + 1 ? pf : (uint64_t)ld_off(rp, r, ow);
       if (v >= k0 && v < kend) atomicAdd(&incl[v - k0], 1u);
       else if (v == kend) atomicAdd(s_extra, 1u);
       stop = v > kend;
@@ -525,49 +541,65 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
   return r0 + tot + *s_extra;
 }
 
-// Payload copies of a lane's kItems cells. When every cell is dword aligned on
-// both sides and at most 32 bytes, all loads are issued before any store;
-// when every cell is at most 16 bytes, bytes move in two batches of four
-// cells; otherwise cell by cell.
-__device__ __forceinline__ void copy_cells(uint8_t* const (&dst)[kItems], const uint8_t* const (&src)[kItems],
-                                           const uint32_t (&sz)[kItems]) {
-  bool small_aligned = true, small = true;
+// Payload copies of a lane's kItems cells, split in two so the caller can
+// put other work (the record stores) between the loads and the stores. When
+// every cell is dword aligned on both sides and at most 32 bytes, the words
+// are loaded into registers up front (`fast`); otherwise the cells are copied
+// one by one in the store phase.
+constexpr int kPay = 4;  // cells per lane whose payload words are held at once
+
+struct PayRegs {
+  uint32_t v[kPay][8];
+  bool fast;
+};
+
+__device__ __forceinline__ void pay_load(PayRegs& P, uint8_t* const (&dst)[kPay],
+                                         const uint8_t* const (&src)[kPay],
+                                         const uint32_t (&sz)[kPay]) {
+  bool fast = true;
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    small_aligned &= sz[r] == 0u ||
-                     (sz[r] <= 32u && ((sz[r] | (uint32_t)(uintptr_t)src[r] | (uint32_t)(uintptr_t)dst[r]) & 3u) == 0);
-    small &= sz[r] <= 16u;
+  for (int r = 0; r < kPay; ++r)
+    fast &= sz[r] == 0u ||
+            (sz[r] <= 32u && ((sz[r] | (uint32_t)(uintptr_t)src[r] | (uint32_t)(uintptr_t)dst[r]) & 3u) == 0);
+  P.fast = fast;
+  if (fast) {
+#pragma unroll
+    for (int r = 0; r < kPay; ++r)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if ((uint32_t)(4 * j) < sz[r]) P.v[r][j] = ((const uint32_t*)src[r])[j];
   }
-  if (small_aligned) {
-    uint32_t v[kItems][8];
+}
+
+__device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst)[kPay],
+                                          const uint8_t* const (&src)[kPay],
+                                          const uint32_t (&sz)[kPay]) {
+  if (P.fast) {
 #pragma unroll
-    for (int r = 0; r < kItems; ++r)
+    for (int r = 0; r < kPay; ++r)
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) v[r][j] = ((const uint32_t*)src[r])[j];
-#pragma unroll
-    for (int r = 0; r < kItems; ++r)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) ((uint32_t*)dst[r])[j] = v[r][j];
-  } else if (small) {
-#pragma unroll
-    for (int h = 0; h < kItems; h += 4) {
-      uint8_t v[4][16];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[h + r]) v[r][j] = src[h + r][j];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[h + r]) dst[h + r][j] = v[r][j];
-    }
+        if ((uint32_t)(4 * j) < sz[r]) ((uint32_t*)dst[r])[j] = P.v[r][j];
   } else {
-    for (int r = 0; r < kItems; ++r)
-      if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
+    bool small = true;
+#pragma unroll
+    for (int r = 0; r < kPay; ++r) small &= sz[r] <= 16u;
+    if (small) {
+      uint8_t v[kPay][16];
+#pragma unroll
+      for (int r = 0; r < kPay; ++r)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if ((uint32_t)j < sz[r]) v[r][j] = src[r][j];
+#pragma unroll
+      for (int r = 0; r < kPay; ++r)
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if ((uint32_t)j < sz[r]) dst[r][j] = v[r][j];
+    } else {
+      for (int r = 0; r < kPay; ++r)
+        if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
+    }
   }
 }
 
@@ -597,17 +629,25 @@ __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const ItemDev* it, ui
   }
 }
 
+// Records of a level buffer: (column, size) pairs and either (row, index)
+// pairs or, when no permutation is wanted, rows alone (12 bytes per cell).
 __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
-                                             uint64_t pos0, uint32_t n) {
+                                             uint64_t pos0, uint32_t n, bool with_idx) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  const uint32_t* rows = (const uint32_t*)rk;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
     S.a[r] = 0; S.b[r] = 0; S.c[r] = 0; S.d[r] = 0;
     if (i < n) {
       const uint2 x = ks[pos0 + i];
-      const uint2 y = rk[pos0 + i];
-      S.a[r] = x.x; S.b[r] = x.y; S.c[r] = y.x; S.d[r] = y.y;
+      S.a[r] = x.x; S.b[r] = x.y;
+      if (with_idx) {
+        const uint2 y = rk[pos0 + i];
+        S.c[r] = y.x; S.d[r] = y.y;
+      } else {
+        S.c[r] = rows[pos0 + i];
+      }
     }
   }
 }
@@ -623,10 +663,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   if (aborted(a.abort_flag)) return;
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
-  if (threadIdx.x == 0) {
-    const uint32_t si = find_seg(a.tstart, a.nseg, tile);
-    s_si = si;
-    s_seg = a.segs[si];
+  {
+    const uint32_t si = coop_find_seg(a.tstart, a.nseg, tile);
+    if (threadIdx.x == 0) {
+      s_si = si;
+      s_seg = a.segs[si];
+    }
   }
   __syncthreads();
   const Seg sg = s_seg;
@@ -653,7 +695,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
   }
   uint32_t r0 = 0;
-  if (pass0) r0 = coop_row_search(it->row_ptr, ow, (uint64_t)it->n_rows, kbase + c_begin);
+  uint64_t rpf = 0;
+  if (pass0) {
+    r0 = coop_row_search(it->row_ptr, ow, (uint64_t)it->n_rows, kbase + c_begin);
+    rpf = prefetch_row(it->row_ptr, ow, (uint64_t)it->n_rows, r0);
+  }
   __syncthreads();
   uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
@@ -662,7 +708,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
     if (pass0) load_sub_pass0(cur, it, kbase + c_begin, n0, ow);
-    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0);
+    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0, a.with_idx);
   }
   for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
     const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
@@ -670,7 +716,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     if (c1 < c_end) {  // next sub-chunk's loads go out now
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
       if (pass0) load_sub_pass0(nxt, it, kbase + c1, n1, ow);
-      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1);
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1, a.with_idx);
     }
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
     uint64_t sub_base;
@@ -678,8 +724,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     if (pass0) {
       const uint64_t kf = kbase + c0;
       sub_base = (uint64_t)ld_off(it->poff, kf, ow);
-      const uint32_t r_next = expand_rows(it->row_ptr, ow, (uint64_t)it->n_rows, kf, n, r0, L.bpre,
-                                          &s_extra, s_red);
+      const uint32_t r_next = expand_rows(it->row_ptr, ow, (uint64_t)it->n_rows, kf, n, r0, rpf,
+                                          L.bpre, &s_extra, s_red);
+      rpf = prefetch_row(it->row_ptr, ow, (uint64_t)it->n_rows, r_next);  // next sub-chunk's rows
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
@@ -716,36 +763,52 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       src_part = owner_of(s_lb, R, (int64_t)first_row);
       xfer_per_cell = owner_of(s_lb, R, (int64_t)last_row) != src_part;
     }
-    // write the sorted cells at their digit's running destination
-    uint8_t* pd[kItems];
-    const uint8_t* ps[kItems];
-    uint32_t pz[kItems];
+    // write the sorted cells at their digit's running destination, kPay
+    // cells per lane at a time: payload loads first, then the records, then
+    // the payload stores
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = r * kBlock + threadIdx.x;
-      pz[r] = 0;
-      pd[r] = a.pay_out;
-      ps[r] = src_base;
-      if (i < n) {
-        const uint32_t d = L.dig[i];
-        const uint32_t ds = L.wc[d * kNW];
-        const uint64_t cd = seg_out + s_rc[d] + (i - ds);
-        const uint64_t bd = s_rb[d] + (L.bpre[i] - L.bpre[ds]);
-        const uint32_t csz = L.sz[i];
-        a.ks_out[cd] = make_uint2(L.key[i], csz);
-        a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
-        pz[r] = csz;
-        pd[r] = a.pay_out + bd;
-        ps[r] = src_base + L.src[i];
-        if (xfer_per_cell) {
-          const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
-          const uint32_t dp = d >> sg.bits;
-          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
-          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)csz);
+    for (int g = 0; g < kItems; g += kPay) {
+      uint8_t* pd[kPay];
+      const uint8_t* ps[kPay];
+      uint32_t pz[kPay];
+      uint64_t cdst[kPay];
+#pragma unroll
+      for (int q = 0; q < kPay; ++q) {
+        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+        pz[q] = 0;
+        pd[q] = a.pay_out;
+        ps[q] = src_base;
+        cdst[q] = 0;
+        if (i < n) {
+          const uint32_t d = L.dig[i];
+          const uint32_t ds = L.wc[d * kNW];
+          cdst[q] = seg_out + s_rc[d] + (i - ds);
+          pz[q] = L.sz[i];
+          pd[q] = a.pay_out + s_rb[d] + (L.bpre[i] - L.bpre[ds]);
+          ps[q] = src_base + L.src[i];
         }
       }
+      PayRegs P;
+      pay_load(P, pd, ps, pz);
+#pragma unroll
+      for (int q = 0; q < kPay; ++q) {
+        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+        if (i < n) {
+          const uint64_t cd = cdst[q];
+          a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
+          if (a.with_idx) a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+          else ((uint32_t*)a.rk_out)[cd] = L.row[i];
+          if (xfer_per_cell) {
+            const uint32_t d = L.dig[i];
+            const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
+            const uint32_t dp = d >> sg.bits;
+            atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
+            atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)pz[q]);
+          }
+        }
+      }
+      pay_store(P, pd, ps, pz);
     }
-    copy_cells(pd, ps, pz);
     if (track_xfer && !xfer_per_cell) {
       const uint32_t sub = 1u << sg.bits;
       for (uint32_t p = threadIdx.x; p < R; p += kBlock) {
@@ -848,11 +911,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 
   uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
   SubLoad cur, nxt;
-  load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len));
+  load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len), a.with_idx);
   for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
     const uint32_t n = min((uint32_t)kSub, len - c0);
     const uint32_t c1 = c0 + kSub;
-    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1), a.with_idx);
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -869,35 +932,48 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
         st_off(t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kNW]), ow);
     }
     const uint8_t* src_base = a.pay_in + src_sub;
-    uint8_t* pd[kItems];
-    const uint8_t* ps[kItems];
-    uint32_t pz[kItems];
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-      const uint32_t i = r * kBlock + threadIdx.x;
-      pz[r] = 0;
-      pd[r] = it->t_payload;
-      ps[r] = src_base;
-      if (i < n) {
-        uint64_t p, b;
-        if (multi) {
-          const uint32_t d = L.dig[i];
-          const uint32_t ds = L.wc[d * kNW];
-          p = out_cell0 + s_cc[d] + (i - ds);
-          b = out_byte0 + s_cb[d] + (L.bpre[i] - L.bpre[ds]);
-        } else {
-          p = out_cell0 + i;
-          b = out_byte0 + L.bpre[i];
+    for (int g = 0; g < kItems; g += kPay) {
+      uint8_t* pd[kPay];
+      const uint8_t* ps[kPay];
+      uint32_t pz[kPay];
+      uint64_t pp[kPay], pb[kPay];
+#pragma unroll
+      for (int q = 0; q < kPay; ++q) {
+        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+        pz[q] = 0;
+        pd[q] = it->t_payload;
+        ps[q] = src_base;
+        pp[q] = 0;
+        pb[q] = 0;
+        if (i < n) {
+          if (multi) {
+            const uint32_t d = L.dig[i];
+            const uint32_t ds = L.wc[d * kNW];
+            pp[q] = out_cell0 + s_cc[d] + (i - ds);
+            pb[q] = out_byte0 + s_cb[d] + (L.bpre[i] - L.bpre[ds]);
+          } else {
+            pp[q] = out_cell0 + i;
+            pb[q] = out_byte0 + L.bpre[i];
+          }
+          pz[q] = L.sz[i];
+          pd[q] = it->t_payload + pb[q];
+          ps[q] = src_base + L.src[i];
         }
-        it->t_col[p] = (int32_t)L.row[i];
-        if (it->perm) it->perm[p] = L.idx[i];
-        st_off(it->t_poff, p, (int64_t)b, ow);
-        pz[r] = L.sz[i];
-        pd[r] = it->t_payload + b;
-        ps[r] = src_base + L.src[i];
       }
+      PayRegs P;
+      pay_load(P, pd, ps, pz);
+#pragma unroll
+      for (int q = 0; q < kPay; ++q) {
+        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+        if (i < n) {
+          it->t_col[pp[q]] = (int32_t)L.row[i];
+          if (it->perm) it->perm[pp[q]] = L.idx[i];
+          st_off(it->t_poff, pp[q], (int64_t)pb[q], ow);
+        }
+      }
+      pay_store(P, pd, ps, pz);
     }
-    copy_cells(pd, ps, pz);
     __syncthreads();
     if (multi) {
       for (uint32_t d = threadIdx.x; d < nc; d += kBlock) {

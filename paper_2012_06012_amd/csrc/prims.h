@@ -158,4 +158,59 @@ __device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8
   }
 }
 
+
+// Wave-cooperative copy of the payloads of 64 cells, one cell per lane
+// (dst, src, sz; sz may be 0). The lanes stride over the concatenation of the
+// 64 payloads, so consecutive lanes touch consecutive words of the same or
+// adjacent cells: one instruction moves 256 contiguous bytes wherever the
+// destinations are contiguous (cells of one digit run). Words are 4 bytes if
+// every cell is 4-byte aligned on both sides with a multiple-of-4 size, else
+// single bytes. The owner of unit x is the last lane whose exclusive unit
+// prefix is <= x (zero-size cells never own a unit), found by a 6-step
+// binary search over lanes with cross-lane shuffles. Loads are issued in
+// groups of four before their stores. Every lane of the wave must call it.
+__device__ __forceinline__ void wave_copy(uint8_t* dst, const uint8_t* src, uint32_t sz) {
+  const uint32_t lane = lane_id();
+  const bool mis = ((uint32_t)(uintptr_t)dst | (uint32_t)(uintptr_t)src | sz) & 3u;
+  const bool words = ballot(sz != 0u && mis) == 0ull;
+  const uint32_t units = words ? (sz >> 2) : sz;
+  const uint32_t incl = wave_incl_scan_u32(units);
+  const uint32_t pre = incl - units;
+  const uint32_t tot = wave_bcast(incl, kWave - 1);
+  const uint64_t s64 = (uint64_t)(uintptr_t)src, d64 = (uint64_t)(uintptr_t)dst;
+  for (uint32_t base = 0; base < tot; base += 4u * kWave) {
+    uint32_t v[4];
+    uint64_t da[4];
+    bool act[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t x = base + (uint32_t)q * kWave + lane;
+      act[q] = x < tot;
+      uint32_t o = 0;
+#pragma unroll
+      for (uint32_t step = 32; step; step >>= 1) {
+        const uint32_t p = __shfl(pre, (int)(o + step), kWave);
+        if (p <= x) o += step;
+      }
+      const uint32_t off = x - __shfl(pre, (int)o, kWave);
+      const uint64_t sa = __shfl(s64, (int)o, kWave);
+      da[q] = __shfl(d64, (int)o, kWave);
+      if (words) {
+        const uint64_t a4 = sa + 4ull * off;
+        da[q] += 4ull * off;
+        v[q] = act[q] ? *(const uint32_t*)(uintptr_t)a4 : 0u;
+      } else {
+        da[q] += off;
+        v[q] = act[q] ? (uint32_t)*(const uint8_t*)(uintptr_t)(sa + off) : 0u;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!act[q]) continue;
+      if (words) *(uint32_t*)(uintptr_t)da[q] = v[q];
+      else *(uint8_t*)(uintptr_t)da[q] = (uint8_t)v[q];
+    }
+  }
+}
+
 }  // namespace mgt

@@ -300,6 +300,16 @@ def from_arrays(n_rows: int, n_cols: int, row_ptr, col, widths=None, payload=Non
                np.asarray(bounds, dtype=np.int64), offset_width, "explicit")
 
 
+def poisson_arrivals(n: int, rate: float, seed: int = 0):
+    """Arrival times (seconds) of a Poisson process of the given rate."""
+    t, out = 0.0, []
+    for i in range(n):
+        u = _unit(draw(seed, 9, i))
+        t += -math.log(1.0 - u) / rate
+        out.append(t)
+    return out
+
+
 CONFIGS = {
     "tiny": tiny,
     "large": large,

@@ -15,6 +15,7 @@ a bit-exactness verdict from sampled output rows.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -32,20 +33,56 @@ def log(*a):
 
 
 def kernel_bytes(a, stage: str, pass_idx: int, perm: bool) -> int:
-    """Algorithmic bytes of one launch of a stage: its inputs read once and its
-    outputs written once (records are 16 bytes per cell in the level buffers)."""
+    """Algorithmic bytes of one launch of a stage: each array it reads counted
+    once and each array it writes counted once (level-buffer records are 16
+    bytes per cell: column, size, row, cell index)."""
     nnz, P, o = a.nnz, a.payload_bytes, a.offset_width
+    rec = nnz * 16
     if stage == "scatter" and pass_idx == 0:
-        return nnz * (4 + 2 * o) + (a.n_rows + 1) * o + P + nnz * 16 + P
+        return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + rec + P
     if stage == "scatter":
-        return 2 * (nnz * 16 + P)
+        return 2 * (rec + P)
     if stage == "finish":
-        return nnz * 16 + P + nnz * (4 + o + (4 if perm else 0)) + (a.n_cols + 1) * o + P
+        return rec + P + nnz * (4 + (4 if perm else 0)) + (nnz + 1) * o + (a.n_cols + 1) * o + P
     if stage == "hist" and pass_idx == 0:
-        return nnz * (4 + 2 * o)
+        return 4 * nnz + (nnz + 1) * o
     if stage == "hist":
         return nnz * 8
     return 0
+
+
+# HBM bytes per launch of a kernel on the default workload (plain transpose
+# of the large multigraph, seed 0), from two profiler counter runs: FETCH_SIZE
+# and WRITE_SIZE in KiB per dispatch, averaged over the kernel's dispatches,
+# each scaled by what the same counter reads for a plain device copy of known
+# size. A reading holds only for the kernel sources it was taken on; after any
+# change to them the traffic figure is reported as null.
+MEASURED_TRAFFIC = {
+    "k_pass_scatter": {"sources_sha256": "0ad76ea24956556fa0fe2d09adebc3d0cb06342e941813a4fa219344f412a94e",
+                       "fetch_kib": 9713033, "write_kib": 22147066},
+    "k_finish": {"sources_sha256": "0ad76ea24956556fa0fe2d09adebc3d0cb06342e941813a4fa219344f412a94e",
+                 "fetch_kib": 12387106, "write_kib": 18601510},
+}
+COPY_SCALE = {"fetch": 2.0, "write": 1.0}
+
+
+def kernel_sources_digest() -> str:
+    d = os.path.join(ROOT, "paper_2012_06012_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kname: str, args):
+    m = MEASURED_TRAFFIC.get(kname)
+    if (m is None or args.partitioned or args.scale or args.seed
+            or m["sources_sha256"] != kernel_sources_digest()):
+        return None
+    return int((m["fetch_kib"] * COPY_SCALE["fetch"] + m["write_kib"] * COPY_SCALE["write"]) * 1024)
 
 
 def copy_calibration(mib: int):
@@ -168,6 +205,139 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def _timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def bench_tiny(args):
+    """1,000 x 1,000, ~20K cells, R = 4: latency of one call (launch bound)."""
+    import torch
+    import oracle
+    from workloads import gen
+    from paper_2012_06012_amd import mgt
+    dev = torch.device("cuda:0")
+    a = gen.tiny(seed=args.seed)
+    d = _device(a, dev)
+    res = {"metric": "latency of one transpose call (tiny multigraph)", "mode": "tiny",
+           "cells": a.nnz, "payload_bytes": a.payload_bytes}
+    for part in (False, True):
+        plan = mgt.plan_for(d)
+        ws = mgt.workspace_for(plan, dev)
+        out = mgt.alloc_outputs(d, partitioned=part)
+        ms = _timed(lambda: mgt.transpose(d, plan=plan, workspace=ws, partitioned=part, out=out),
+                    max(args.steps, 50), 5)
+        h = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        ref = oracle.transpose(a)
+        exact = all(np.array_equal(h[k], getattr(ref, k)) for k in
+                    ("t_row_ptr", "t_col", "t_payload_off", "t_payload"))
+        res["partitioned" if part else "plain"] = {"us_per_call": ms * 1e3,
+                                                   "cells_per_s": a.nnz / (ms * 1e-3),
+                                                   "bit_exact": bool(exact)}
+    print(json.dumps(res), flush=True)
+
+
+def bench_hetero(args):
+    """Heterogeneously balanced multigraph, partitioned (R = 256): 2^21 x 2^21,
+    2^30 cells, 28-byte payload; sampled output rows checked against the oracle."""
+    import torch
+    import oracle
+    from workloads import gen
+    from paper_2012_06012_amd import mgt
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    a = gen.hetero(seed=args.seed, scale=args.scale)
+    log(f"[hetero] generated nnz={a.nnz} payload={a.payload_bytes} in {time.time() - t0:.1f}s")
+    d = _device(a, dev)
+    plan = mgt.plan_for(d)
+    ws = mgt.workspace_for(plan, dev)
+    out = mgt.alloc_outputs(d, partitioned=True)
+    ms = _timed(lambda: mgt.transpose(d, plan=plan, workspace=ws, partitioned=True, out=out),
+                args.steps, args.warmup)
+    t_row_ptr = out["t_row_ptr"].cpu().numpy()
+    ok = bool(np.array_equal(np.diff(t_row_ptr), np.bincount(a.col, minlength=a.n_cols)))
+    pc = out["part_cell_off"].cpu().numpy()
+    ok &= bool(np.array_equal(pc, t_row_ptr[a.bounds]))
+    rng = np.random.default_rng(args.seed + 5)
+    for lo in [0, a.n_cols - 32] + [int(c) for c in rng.integers(0, a.n_cols - 32, size=3)]:
+        s = oracle.transpose_columns(a, lo, lo + 32)
+        p0, p1 = int(t_row_ptr[lo]), int(t_row_ptr[lo + 32])
+        ok &= bool(np.array_equal(out["t_col"][p0:p1].cpu().numpy(), s.t_col))
+        po = out["t_payload_off"][p0:p1 + 1].cpu().numpy()
+        ok &= bool(np.array_equal(out["t_payload"][int(po[0]):int(po[-1])].cpu().numpy(),
+                                  s.t_payload))
+    b_alg = a.algorithmic_bytes(partitioned=True)
+    res = {"metric": "cells/s (partitioned transpose, bit-exact sampled)", "mode": "hetero",
+           "value": a.nnz / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
+           "hbm_frac_step": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bit_exact_sampled": ok,
+           "config": {"workload": "heterogeneous multigraph 2^21 x 2^21, 2^30 cells, 28-byte "
+                                  "payload, R=256", "scale_shift": args.scale,
+                      "nnz": a.nnz, "payload_bytes": a.payload_bytes}}
+    print(json.dumps(res), flush=True)
+
+
+def bench_involution(args):
+    """The paper's check (Section 4): 12 composed transposes of one dataset on
+    device-resident ping-pong buffers; T^12(A) must equal T^2(A), which is A
+    itself when A's rows are column ordered (the generator's default)."""
+    import torch
+    from workloads import gen
+    from paper_2012_06012_amd import mgt
+    dev = torch.device("cuda:0")
+    a = gen.large(seed=args.seed, scale=args.scale if args.scale else 3)
+    d = _device(a, dev)
+    plan = mgt.plan_for(d)
+    ws = mgt.workspace_for(plan, dev)
+    bufs = [mgt.alloc_outputs(d), mgt.alloc_outputs(d)]
+    orig = {k: v.clone() for k, v in (("row_ptr", d.row_ptr), ("col", d.col),
+                                      ("payload_off", d.payload_off), ("payload", d.payload))}
+
+    def twelve():
+        x = d
+        for i in range(12):
+            o = bufs[i & 1]
+            mgt.transpose(x, plan=plan, workspace=ws, out=o)
+            x = mgt.DeviceCsr(x.n_cols, x.n_rows, o["t_row_ptr"], o["t_col"], o["t_payload_off"],
+                              o["t_payload"], x.bounds, x.offset_width)
+        return x
+    def same(x, ref):
+        return bool(torch.equal(x.row_ptr, ref["row_ptr"]) and torch.equal(x.col, ref["col"]) and
+                    torch.equal(x.payload_off, ref["payload_off"]) and
+                    torch.equal(x.payload, ref["payload"]))
+
+    # T(T(A)) is A with each row's cells ordered by column (ties keep their
+    # order); every later even power must reproduce it exactly
+    o1 = mgt.alloc_outputs(d)
+    mgt.transpose(d, plan=plan, workspace=ws, out=o1)
+    t1 = mgt.DeviceCsr(d.n_cols, d.n_rows, o1["t_row_ptr"], o1["t_col"], o1["t_payload_off"],
+                       o1["t_payload"], d.bounds, d.offset_width)
+    o2 = mgt.alloc_outputs(d)
+    mgt.transpose(t1, plan=plan, workspace=ws, out=o2)
+    torch.cuda.synchronize()
+    t2 = {"row_ptr": o2["t_row_ptr"], "col": o2["t_col"], "payload_off": o2["t_payload_off"],
+          "payload": o2["t_payload"]}
+    x = twelve()
+    torch.cuda.synchronize()
+    ok12 = same(x, t2)
+    ok2 = same(mgt.DeviceCsr(d.n_rows, d.n_cols, t2["row_ptr"], t2["col"], t2["payload_off"],
+                             t2["payload"], d.bounds, d.offset_width), orig)
+    ms = _timed(twelve, max(1, args.steps // 3), 1)
+    res = {"metric": "12 composed transposes (paper's involution check)", "mode": "involution",
+           "ms_for_12": ms, "cells_per_s": 12 * a.nnz / (ms * 1e-3), "T12_equals_T2": ok12,
+           "T2_equals_A": ok2,
+           "config": {"workload": "large multigraph", "scale_shift": args.scale if args.scale else 3}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +352,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this size (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters and measures copy bandwidth)")
-    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain",
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "tiny", "hetero", "involution"],
+                    default="plain",
                     help="plain: the headline line; batch: many matrices in one mgt_batch_submit "
                          "vs per-matrix launches; serve: the continuous-batching request loop vs "
                          "per-request plain launches")
@@ -194,6 +365,12 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "tiny":
+        return bench_tiny(args)
+    if args.mode == "hetero":
+        return bench_hetero(args)
+    if args.mode == "involution":
+        return bench_involution(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
               "multi-GPU path; see DESIGN.md for how the transpose would shard.", file=sys.stderr)
@@ -253,13 +430,25 @@ def main():
             acc.setdefault((name, k), []).append(v)
     stages = {f"{n}{k}": float(np.mean(v)) for (n, k), v in acc.items()}
     log(f"[bench] stages (ms): {json.dumps({k: round(v, 3) for k, v in stages.items()})}")
-    dom_key = max((k for k in stages if k.startswith(("scatter", "finish", "hist"))),
-                  key=lambda k: stages[k])
-    dom_stage = dom_key.rstrip("0123456789")
-    dom_pass = int(dom_key[len(dom_stage):] or 0)
-    dom_bytes = kernel_bytes(a, dom_stage, dom_pass, False)
-    dom_ms = stages[dom_key]
+    # dominant kernel = the one with the most device time per step; its figures
+    # are averages over its launches in a step, as a profiler's per-kernel
+    # average duration is
+    per_kernel = {}
+    for key, v in stages.items():
+        st = key.rstrip("0123456789")
+        if st not in ("scatter", "finish", "hist"):
+            continue
+        pidx = int(key[len(st):] or 0)
+        e = per_kernel.setdefault(st, [0.0, 0, 0])
+        e[0] += v
+        e[1] += kernel_bytes(a, st, pidx, False)
+        e[2] += 1
+    dom_stage = max(per_kernel, key=lambda k: per_kernel[k][0])
+    dom_ms = per_kernel[dom_stage][0] / per_kernel[dom_stage][2]
+    dom_bytes = per_kernel[dom_stage][1] // per_kernel[dom_stage][2]
+    dom_launches = per_kernel[dom_stage][2]
     kname = {"scatter": "k_pass_scatter", "finish": "k_finish", "hist": "k_pass_hist"}[dom_stage]
+    traffic = measured_traffic(kname, args)
 
     b_alg = a.algorithmic_bytes(partitioned=part)
     value = a.nnz / (ms * 1e-3)
@@ -328,10 +517,10 @@ def main():
         "algorithmic_bytes_step": b_alg,
         "bit_exact_sampled": exact,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
-        "roofline": {"bound": "hbm", "kernel": kname, "launch": dom_key,
+        "roofline": {"bound": "hbm", "kernel": kname, "launches_per_step": dom_launches,
                      "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms},
+                     "traffic": traffic, "bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms},
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

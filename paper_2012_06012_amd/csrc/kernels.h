@@ -21,7 +21,7 @@ struct PassArgs {
   const uint64_t* tstart;     // nseg + 1
   const uint64_t* hstart;     // nseg + 1
   const uint2* ks_in;         // (key, size) records, pass >= 2
-  const uint2* rk_in;         // (row, index) records, pass >= 2
+  const uint2* rk_in;         // (row, cell index) records, pass >= 2
   const uint8_t* pay_in;      // payload bytes, pass >= 2
   uint2* ks_out;
   uint2* rk_out;
@@ -37,7 +37,6 @@ struct PassArgs {
   uint64_t g8;                // grid size (multiple of 8)
   uint32_t tile_cells;        // multiple of kSub
   int32_t offset_width;
-  int32_t with_idx;           // records carry the input cell index (for perm)
 };
 
 struct ChildArgs {
@@ -65,7 +64,6 @@ struct FinishArgs {
   const uint8_t* pay_in;
   const int32_t* abort_flag;
   int32_t offset_width;
-  int32_t with_idx;
   uint64_t g8;                // grid size (multiple of 8)
 };
 

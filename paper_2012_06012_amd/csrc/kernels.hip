@@ -22,11 +22,32 @@ static_assert(kItems * kWave * kNW == kSub, "sub-chunk geometry");
 // ----------------------------------------------------------------------------- helpers
 
 __device__ __forceinline__ int64_t ld_off(const void* p, uint64_t i, int ow) {
-  return ow == 4 ? (int64_t)((const int32_t*)p)[i] : ((const int64_t*)p)[i];
+  return ow == 4 ? (int64_t)gm((const int32_t*)p)[i] : gm((const int64_t*)p)[i];
+}
+// Low 32-bit word of offset i of an array of 2^lg-byte little-endian offsets
+// (lg = 2 or 3). One load of the same type for both widths, so a run of them
+// can be in flight at once; differences of low words are exact whenever the
+// true difference is below 2^32.
+__device__ __forceinline__ uint32_t ld_lo(const void* p, uint64_t i, int lg) {
+  return *gm((const uint32_t*)((const uint8_t*)p + (i << lg)));
+}
+// Full offset i, read as two words without a branch on the width (for 4-byte
+// offsets the second load re-reads word i, so it stays inside the array).
+__device__ __forceinline__ uint64_t ld_full(const void* p, uint64_t i, int lg) {
+  const uint8_t* a = (const uint8_t*)p + (i << lg);
+  const uint32_t lo = *gm((const uint32_t*)a);
+  const uint32_t hi = *gm((const uint32_t*)(a + (lg == 3 ? 4 : 0)));
+  return (uint64_t)lo | ((uint64_t)(lg == 3 ? hi : 0u) << 32);
 }
 __device__ __forceinline__ void st_off(void* p, uint64_t i, int64_t v, int ow) {
-  if (ow == 4) ((int32_t*)p)[i] = (int32_t)v;
-  else ((int64_t*)p)[i] = v;
+  if (ow == 4) gm((int32_t*)p)[i] = (int32_t)v;
+  else gm((int64_t*)p)[i] = v;
+}
+
+// Relaxed device-scope add on a 64-bit counter in global memory.
+__device__ __forceinline__ void add_u64(uint64_t* p, uint64_t v) {
+  __hip_atomic_fetch_add(gm((unsigned long long*)p), (unsigned long long)v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
@@ -279,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   const uint32_t R = (uint32_t)it->n_parts;
   const uint32_t F = seg_fanout(sg, R);
   if (sg.mode)
-    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)it->bounds[i];
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
   for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
     s_cnt[d] = 0;
     s_byt[d] = 0;
@@ -295,28 +316,26 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
     const int32_t* col = it->col;
     const void* poff = it->poff;
+    const int lg = ow == 8 ? 3 : 2;
+    // the tile's bytes exactly; below 2^32 they make every low-word size exact
+    mybytes = threadIdx.x == 0 ? ld_full(poff, kbase + c_end, lg) - ld_full(poff, kbase + c_begin, lg) : 0;
     for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
-      uint32_t key[kBatch];
-      int64_t p0[kBatch], p1[kBatch];
+      uint32_t key[kBatch], p0[kBatch], p1[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const uint64_t cc = c + (uint64_t)q * kBlock;
-        key[q] = 0; p0[q] = 0; p1[q] = 0;
-        if (cc < c_end) {
-          const uint64_t k = kbase + cc;
-          key[q] = (uint32_t)col[k];
-          p0[q] = ld_off(poff, k, ow);
-          p1[q] = ld_off(poff, k + 1, ow);
-        }
+        const uint64_t cc = min(c + (uint64_t)q * kBlock, c_end - 1);  // in bounds, no branch
+        const uint64_t k = kbase + cc;
+        key[q] = (uint32_t)gm(col)[k];
+        p0[q] = ld_lo(poff, k, lg);
+        p1[q] = ld_lo(poff, k + 1, lg);
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         if (c + (uint64_t)q * kBlock < c_end) {
-          const uint32_t sz = (uint32_t)(p1[q] - p0[q]);
+          const uint32_t sz = p1[q] - p0[q];
           const uint32_t d = digit_of(key[q], sg, s_lb, R);
           atomicAdd(&s_cnt[d], 1u);
           atomicAdd(&s_byt[d], sz);
-          mybytes += sz;
         }
       }
     }
@@ -325,9 +344,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       uint2 ks[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        const uint64_t cc = c + (uint64_t)q * kBlock;
-        ks[q] = make_uint2(0, 0);
-        if (cc < c_end) ks[q] = a.ks_in[sg.cell0 + cc];
+        const uint64_t cc = min(c + (uint64_t)q * kBlock, c_end - 1);
+        ks[q] = a.ks_in[sg.cell0 + cc];
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -567,7 +585,7 @@ __device__ __forceinline__ void pay_load(PayRegs& P, uint8_t* const (&dst)[kPay]
     for (int r = 0; r < kPay; ++r)
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) P.v[r][j] = ((const uint32_t*)src[r])[j];
+        if ((uint32_t)(4 * j) < sz[r]) P.v[r][j] = gm((const uint32_t*)src[r])[j];
   }
 }
 
@@ -579,7 +597,7 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
     for (int r = 0; r < kPay; ++r)
 #pragma unroll
       for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) ((uint32_t*)dst[r])[j] = P.v[r][j];
+        if ((uint32_t)(4 * j) < sz[r]) gm((uint32_t*)dst[r])[j] = P.v[r][j];
   } else {
     bool small = true;
 #pragma unroll
@@ -590,12 +608,12 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
       for (int r = 0; r < kPay; ++r)
 #pragma unroll
         for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[r]) v[r][j] = src[r][j];
+          if ((uint32_t)j < sz[r]) v[r][j] = gm(src[r])[j];
 #pragma unroll
       for (int r = 0; r < kPay; ++r)
 #pragma unroll
         for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[r]) dst[r][j] = v[r][j];
+          if ((uint32_t)j < sz[r]) gm(dst[r])[j] = v[r][j];
     } else {
       for (int r = 0; r < kPay; ++r)
         if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
@@ -606,49 +624,57 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
 // ----------------------------------------------------------------------------- pass: scatter
 
 // Loads of one sub-chunk, kept in registers so the next sub-chunk can be in
-// flight while the current one is sorted and written.
+// flight while the current one is sorted and written. Every load is issued
+// unconditionally (indexes clamped into the range) and nothing is computed
+// from a loaded value here, so the compiler has no reason to wait for one
+// load before issuing the next.
+//   pass 0:   a = column, c = low word of the payload offset; `pend` = low word
+//             of the offset after the wave's last cell, `base` = full offset of
+//             the sub-chunk's first cell
+//   pass >=1: a = column, b = size, c = row, d = cell index
 struct SubLoad {
   uint32_t a[kItems], b[kItems], c[kItems], d[kItems];
+  uint32_t pend;
+  uint64_t base;
 };
 
-__device__ __forceinline__ void load_sub_pass0(SubLoad& S, const ItemDev* it, uint64_t kfirst,
-                                               uint32_t n, int ow) {
+__device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, const void* poff,
+                                               uint64_t kfirst, uint32_t n, int lg) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
-    S.a[r] = 0; S.b[r] = 0; S.c[r] = 0; S.d[r] = 0;
-    if (i < n) {
-      const uint64_t k = kfirst + i;
-      S.a[r] = (uint32_t)it->col[k];
-      const int64_t p0 = ld_off(it->poff, k, ow), p1 = ld_off(it->poff, k + 1, ow);
-      S.b[r] = (uint32_t)(p1 - p0);
-      S.c[r] = (uint32_t)p0;           // low and high words of the payload offset
-      S.d[r] = (uint32_t)((uint64_t)p0 >> 32);
-    }
+    S.a[r] = (uint32_t)gm(col)[kfirst + min(i, n - 1)];
+    S.c[r] = ld_lo(poff, kfirst + min(i, n), lg);  // the offset array has one more entry
+  }
+  S.pend = ld_lo(poff, kfirst + min(w * kWaveCells + kWaveCells, n), lg);
+  S.base = ld_full(poff, kfirst, lg);
+}
+
+__device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
+                                             uint64_t pos0, uint32_t n) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
+    const uint2 x = ks[pos0 + i];
+    const uint2 y = rk[pos0 + i];
+    S.a[r] = x.x; S.b[r] = x.y; S.c[r] = y.x; S.d[r] = y.y;
   }
 }
 
-// Records of a level buffer: (column, size) pairs and either (row, index)
-// pairs or, when no permutation is wanted, rows alone (12 bytes per cell).
-__device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
-                                             uint64_t pos0, uint32_t n, bool with_idx) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
-  const uint32_t* rows = (const uint32_t*)rk;
+// Payload sizes of a pass-0 sub-chunk from the low offset words: each cell's
+// size is the next cell's offset minus its own (the next cell is the next
+// lane, or lane 0 of the next register, or the wave's `pend`).
+__device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&sz)[kItems]) {
+  const uint32_t lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = w * kWaveCells + r * kWave + lane;
-    S.a[r] = 0; S.b[r] = 0; S.c[r] = 0; S.d[r] = 0;
-    if (i < n) {
-      const uint2 x = ks[pos0 + i];
-      S.a[r] = x.x; S.b[r] = x.y;
-      if (with_idx) {
-        const uint2 y = rk[pos0 + i];
-        S.c[r] = y.x; S.d[r] = y.y;
-      } else {
-        S.c[r] = rows[pos0 + i];
-      }
-    }
+    uint32_t nx = (uint32_t)__shfl_down((int)S.c[r], 1);
+    const uint32_t wrap = r + 1 < kItems ? (uint32_t)__builtin_amdgcn_readlane((int)S.c[r + 1 < kItems ? r + 1 : r], 0)
+                                         : S.pend;
+    if (lane == kWave - 1) nx = wrap;
+    sz[r] = nx - S.c[r];
   }
 }
 
@@ -686,10 +712,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   const bool pass0 = a.pass == 0;
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
   const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
+  // item fields used in the loop, read once
+  const int32_t* const i_col = it->col;
+  const void* const i_poff = it->poff;
+  const void* const i_rp = it->row_ptr;
+  const uint64_t i_nrows = (uint64_t)it->n_rows;
+  const uint8_t* const i_pay = it->payload;
+  const int lg = ow == 8 ? 3 : 2;
   const uint64_t seg_out = sg.cell0;  // a segment's children share its cell range
 
   if (sg.mode)
-    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)it->bounds[i];
+    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
   for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
     s_rc[d] = (uint32_t)(a.ocnt[hb + (uint64_t)d * nt + j] - seg_out);
     s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
@@ -697,8 +730,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   uint32_t r0 = 0;
   uint64_t rpf = 0;
   if (pass0) {
-    r0 = coop_row_search(it->row_ptr, ow, (uint64_t)it->n_rows, kbase + c_begin);
-    rpf = prefetch_row(it->row_ptr, ow, (uint64_t)it->n_rows, r0);
+    r0 = coop_row_search(i_rp, ow, i_nrows, kbase + c_begin);
+    rpf = prefetch_row(i_rp, ow, i_nrows, r0);
   }
   __syncthreads();
   uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
@@ -707,33 +740,31 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if (pass0) load_sub_pass0(cur, it, kbase + c_begin, n0, ow);
-    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0, a.with_idx);
+    if (pass0) load_sub_pass0(cur, i_col, i_poff, kbase + c_begin, n0, lg);
+    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0);
   }
   for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
     const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
     const uint64_t c1 = c0 + kSub;
     if (c1 < c_end) {  // next sub-chunk's loads go out now
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if (pass0) load_sub_pass0(nxt, it, kbase + c1, n1, ow);
-      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1, a.with_idx);
+      if (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg);
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1);
     }
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
     uint64_t sub_base;
     uint32_t first_row = 0, last_row = 0;
     if (pass0) {
       const uint64_t kf = kbase + c0;
-      sub_base = (uint64_t)ld_off(it->poff, kf, ow);
-      const uint32_t r_next = expand_rows(it->row_ptr, ow, (uint64_t)it->n_rows, kf, n, r0, rpf,
-                                          L.bpre, &s_extra, s_red);
-      rpf = prefetch_row(it->row_ptr, ow, (uint64_t)it->n_rows, r_next);  // next sub-chunk's rows
+      sub_base = cur.base;
+      const uint32_t r_next = expand_rows(i_rp, ow, i_nrows, kf, n, r0, rpf, L.bpre, &s_extra, s_red);
+      rpf = prefetch_row(i_rp, ow, i_nrows, r_next);  // next sub-chunk's rows
+      sizes_from_offsets(cur, sz);
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
         key[r] = cur.a[r];
-        sz[r] = cur.b[r];
-        const uint64_t p0 = (uint64_t)cur.c[r] | ((uint64_t)cur.d[r] << 32);
-        src[r] = (uint32_t)(p0 - sub_base);
+        src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
         row[r] = i < n ? r0 + L.bpre[i] : 0u;
         idx[r] = (uint32_t)(kf + i);
       }
@@ -745,7 +776,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       sub_base = src_sub;
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
-        key[r] = cur.a[r]; sz[r] = cur.b[r]; row[r] = cur.c[r]; idx[r] = cur.d[r];
+        const uint32_t i = w * kWaveCells + r * kWave + lane;
+        key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
       }
       src_sub += sub_src_prefix(sz, src, s_red);
     }
@@ -756,7 +788,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     }
     sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
 
-    const uint8_t* src_base = pass0 ? it->payload + sub_base : a.pay_in + sub_base;
+    const uint8_t* src_base = pass0 ? i_pay + sub_base : a.pay_in + sub_base;
     bool xfer_per_cell = false;
     uint32_t src_part = 0;
     if (track_xfer) {
@@ -796,14 +828,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
         if (i < n) {
           const uint64_t cd = cdst[q];
           a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
-          if (a.with_idx) a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
-          else ((uint32_t*)a.rk_out)[cd] = L.row[i];
+          a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
           if (xfer_per_cell) {
             const uint32_t d = L.dig[i];
             const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
             const uint32_t dp = d >> sg.bits;
-            atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
-            atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)sp * R + dp], (unsigned long long)pz[q]);
+            add_u64((uint64_t*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
+            add_u64((uint64_t*)&it->xfer_bytes[(uint64_t)sp * R + dp], (uint64_t)pz[q]);
           }
         }
       }
@@ -816,10 +847,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
         const uint32_t i0 = L.wc[d0 * kNW];
         const uint32_t i1 = d1 < F ? L.wc[d1 * kNW] : n;
         if (i1 > i0) {
-          atomicAdd((unsigned long long*)&it->xfer_cells[(uint64_t)src_part * R + p],
-                    (unsigned long long)(i1 - i0));
-          atomicAdd((unsigned long long*)&it->xfer_bytes[(uint64_t)src_part * R + p],
-                    (unsigned long long)(L.bpre[i1] - L.bpre[i0]));
+          add_u64((uint64_t*)&it->xfer_cells[(uint64_t)src_part * R + p], (uint64_t)(i1 - i0));
+          add_u64((uint64_t*)&it->xfer_bytes[(uint64_t)src_part * R + p],
+                  (uint64_t)(L.bpre[i1] - L.bpre[i0]));
         }
       }
     }
@@ -858,6 +888,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   const bool multi = len > (uint32_t)kSub;
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
   void* t_row_ptr = it->t_row_ptr;
+  uint8_t* const o_pay = it->t_payload;
+  int32_t* const o_col = it->t_col;
+  uint32_t* const o_perm = (uint32_t*)it->perm;
+  void* const o_poff = it->t_poff;
 
   if (multi) {
     for (uint32_t c = threadIdx.x; c < nc; c += kBlock) {
@@ -869,11 +903,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
     for (uint32_t c = threadIdx.x; c < len; c += kStride) {
       uint2 ks[kBatch];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q) {
-        const uint32_t cc = c + q * kBlock;
-        ks[q] = make_uint2(sg.key_lo, 0);
-        if (cc < len) ks[q] = a.ks_in[sg.cell0 + cc];
-      }
+      for (int q = 0; q < kBatch; ++q) ks[q] = a.ks_in[sg.cell0 + min(c + q * kBlock, len - 1)];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         if (c + q * kBlock < len) {
@@ -911,16 +941,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 
   uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
   SubLoad cur, nxt;
-  load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len), a.with_idx);
+  if (len) load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len));
   for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
     const uint32_t n = min((uint32_t)kSub, len - c0);
     const uint32_t c1 = c0 + kSub;
-    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1), a.with_idx);
+    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
-      key[r] = cur.a[r]; sz[r] = cur.b[r]; row[r] = cur.c[r]; idx[r] = cur.d[r];
+      key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
       const uint32_t d = key[r] - sg.key_lo;
       dg[r] = i < n ? (d < nc ? d : nc - 1) : 0u;
     }
@@ -942,7 +972,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       for (int q = 0; q < kPay; ++q) {
         const uint32_t i = (g + q) * kBlock + threadIdx.x;
         pz[q] = 0;
-        pd[q] = it->t_payload;
+        pd[q] = o_pay;
         ps[q] = src_base;
         pp[q] = 0;
         pb[q] = 0;
@@ -957,7 +987,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
             pb[q] = out_byte0 + L.bpre[i];
           }
           pz[q] = L.sz[i];
-          pd[q] = it->t_payload + pb[q];
+          pd[q] = o_pay + pb[q];
           ps[q] = src_base + L.src[i];
         }
       }
@@ -967,9 +997,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       for (int q = 0; q < kPay; ++q) {
         const uint32_t i = (g + q) * kBlock + threadIdx.x;
         if (i < n) {
-          it->t_col[pp[q]] = (int32_t)L.row[i];
-          if (it->perm) it->perm[pp[q]] = L.idx[i];
-          st_off(it->t_poff, pp[q], (int64_t)pb[q], ow);
+          gm(o_col)[pp[q]] = (int32_t)L.row[i];
+          if (o_perm) gm(o_perm)[pp[q]] = L.idx[i];
+          st_off(o_poff, pp[q], (int64_t)pb[q], ow);
         }
       }
       pay_store(P, pd, ps, pz);

@@ -95,15 +95,27 @@ __device__ __forceinline__ uint64_t xcd_tile(uint64_t b, uint64_t g8) {
   return (b & 7u) * (g8 >> 3) + (b >> 3);
 }
 
+// Global-memory (address space 1) views of generic pointers. Accesses through
+// them compile to global_* instructions, which only the vector-memory counter
+// tracks; flat_* accesses are tracked by the LDS counter as well, so every
+// wait for an LDS result would also wait for all outstanding HBM traffic.
+#define GMEM __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GMEM T* gm(T* p) { return (GMEM T*)p; }
+template <typename T>
+__device__ __forceinline__ const GMEM T* gm(const T* p) { return (const GMEM T*)p; }
+
 // Copies one cell's payload (any width, any alignment). Every chunk issues
 // all of its loads before its stores, so a lane waits for memory once per
 // chunk instead of once per word. Source and destination sharing their
 // alignment modulo 4 move as 4-byte words (up to 8 per chunk); otherwise as
 // bytes (up to 16 per chunk).
-__device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8_t* __restrict__ src,
+__device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst_, const uint8_t* __restrict__ src_,
                                           uint32_t n) {
-  if ((((uintptr_t)dst ^ (uintptr_t)src) & 3u) == 0) {
-    uint32_t h = (4u - ((uintptr_t)dst & 3u)) & 3u;
+  GMEM uint8_t* dst = gm(dst_);
+  const GMEM uint8_t* src = gm(src_);
+  if ((((uintptr_t)dst_ ^ (uintptr_t)src_) & 3u) == 0) {
+    uint32_t h = (4u - ((uintptr_t)dst_ & 3u)) & 3u;
     h = h < n ? h : n;
     uint8_t hb[3];
 #pragma unroll
@@ -115,8 +127,8 @@ __device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8
     dst += h;
     src += h;
     n -= h;
-    const uint32_t* s4 = (const uint32_t*)src;
-    uint32_t* d4 = (uint32_t*)dst;
+    const GMEM uint32_t* s4 = (const GMEM uint32_t*)src;
+    GMEM uint32_t* d4 = (GMEM uint32_t*)dst;
     uint32_t w = n >> 2;
     while (w) {
       const uint32_t m = w < 8u ? w : 8u;
@@ -132,8 +144,8 @@ __device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8
       w -= m;
     }
     const uint32_t t = n & 3u;
-    const uint8_t* sb = (const uint8_t*)s4;
-    uint8_t* db = (uint8_t*)d4;
+    const GMEM uint8_t* sb = (const GMEM uint8_t*)s4;
+    GMEM uint8_t* db = (GMEM uint8_t*)d4;
     uint8_t tb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j)
@@ -154,61 +166,6 @@ __device__ __forceinline__ void copy_cell(uint8_t* __restrict__ dst, const uint8
       src += m;
       dst += m;
       n -= m;
-    }
-  }
-}
-
-
-// Wave-cooperative copy of the payloads of 64 cells, one cell per lane
-// (dst, src, sz; sz may be 0). The lanes stride over the concatenation of the
-// 64 payloads, so consecutive lanes touch consecutive words of the same or
-// adjacent cells: one instruction moves 256 contiguous bytes wherever the
-// destinations are contiguous (cells of one digit run). Words are 4 bytes if
-// every cell is 4-byte aligned on both sides with a multiple-of-4 size, else
-// single bytes. The owner of unit x is the last lane whose exclusive unit
-// prefix is <= x (zero-size cells never own a unit), found by a 6-step
-// binary search over lanes with cross-lane shuffles. Loads are issued in
-// groups of four before their stores. Every lane of the wave must call it.
-__device__ __forceinline__ void wave_copy(uint8_t* dst, const uint8_t* src, uint32_t sz) {
-  const uint32_t lane = lane_id();
-  const bool mis = ((uint32_t)(uintptr_t)dst | (uint32_t)(uintptr_t)src | sz) & 3u;
-  const bool words = ballot(sz != 0u && mis) == 0ull;
-  const uint32_t units = words ? (sz >> 2) : sz;
-  const uint32_t incl = wave_incl_scan_u32(units);
-  const uint32_t pre = incl - units;
-  const uint32_t tot = wave_bcast(incl, kWave - 1);
-  const uint64_t s64 = (uint64_t)(uintptr_t)src, d64 = (uint64_t)(uintptr_t)dst;
-  for (uint32_t base = 0; base < tot; base += 4u * kWave) {
-    uint32_t v[4];
-    uint64_t da[4];
-    bool act[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t x = base + (uint32_t)q * kWave + lane;
-      act[q] = x < tot;
-      uint32_t o = 0;
-#pragma unroll
-      for (uint32_t step = 32; step; step >>= 1) {
-        const uint32_t p = __shfl(pre, (int)(o + step), kWave);
-        if (p <= x) o += step;
-      }
-      const uint32_t off = x - __shfl(pre, (int)o, kWave);
-      const uint64_t sa = __shfl(s64, (int)o, kWave);
-      da[q] = __shfl(d64, (int)o, kWave);
-      if (words) {
-        const uint64_t a4 = sa + 4ull * off;
-        da[q] += 4ull * off;
-        v[q] = act[q] ? *(const uint32_t*)(uintptr_t)a4 : 0u;
-      } else {
-        da[q] += off;
-        v[q] = act[q] ? (uint32_t)*(const uint8_t*)(uintptr_t)(sa + off) : 0u;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!act[q]) continue;
-      if (words) *(uint32_t*)(uintptr_t)da[q] = v[q];
-      else *(uint8_t*)(uintptr_t)da[q] = (uint8_t)v[q];
     }
   }
 }

@@ -387,7 +387,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.g8 = align_up(y.tiles_max[l], 8);
     a.tile_cells = kTileCells;
     a.offset_width = ow;
-    a.with_idx = 1;  // (row, index) pairs measured faster than rows alone
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];
@@ -424,7 +423,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.pay_in = (const uint8_t*)(W + y.o_pay[bl]);
   f.abort_flag = d_abort;
   f.offset_width = ow;
-  f.with_idx = 1;
   f.g8 = align_up(y.nseg[L], 8);
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");

@@ -32,18 +32,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(a, stage: str, pass_idx: int, perm: bool) -> int:
+def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int:
     """Algorithmic bytes of one launch of a stage: each array it reads counted
-    once and each array it writes counted once (level-buffer records are 16
-    bytes per cell: column, size, row, cell index)."""
+    once and each array it writes counted once. Level-buffer records are 16
+    bytes per cell (column, size, row, cell index); with two or more passes the
+    last one moves records only and adds an 8-byte payload offset per cell,
+    which the finish reads to fetch each payload."""
     nnz, P, o = a.nnz, a.payload_bytes, a.offset_width
     rec = nnz * 16
+    deferred = n_passes >= 2
     if stage == "scatter" and pass_idx == 0:
         return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + rec + P
+    if stage == "scatter" and deferred and pass_idx == n_passes - 1:
+        return rec + rec + 8 * nnz
     if stage == "scatter":
         return 2 * (rec + P)
     if stage == "finish":
-        return rec + P + nnz * (4 + (4 if perm else 0)) + (nnz + 1) * o + (a.n_cols + 1) * o + P
+        return (rec + (8 * nnz if deferred else 0) + P + nnz * (4 + (4 if perm else 0))
+                + (nnz + 1) * o + (a.n_cols + 1) * o + P)
     if stage == "hist" and pass_idx == 0:
         return 4 * nnz + (nnz + 1) * o
     if stage == "hist":
@@ -434,6 +440,7 @@ def main():
     # are averages over its launches in a step, as a profiler's per-kernel
     # average duration is
     per_kernel = {}
+    n_passes = sum(1 for k in stages if k.rstrip("0123456789") == "scatter")
     for key, v in stages.items():
         st = key.rstrip("0123456789")
         if st not in ("scatter", "finish", "hist"):
@@ -441,7 +448,7 @@ def main():
         pidx = int(key[len(st):] or 0)
         e = per_kernel.setdefault(st, [0.0, 0, 0])
         e[0] += v
-        e[1] += kernel_bytes(a, st, pidx, False)
+        e[1] += kernel_bytes(a, st, pidx, False, n_passes)
         e[2] += 1
     dom_stage = max(per_kernel, key=lambda k: per_kernel[k][0])
     dom_ms = per_kernel[dom_stage][0] / per_kernel[dom_stage][2]

@@ -515,9 +515,19 @@ __device__ __forceinline__ uint32_t coop_row_search(const void* rp, int ow, uint
 // LDS). Returns the row of cell k0 + n. Every thread must call it.
 // `pf` is row_ptr[r0 + 1 + threadIdx.x] (or ~0 past the last row), loaded
 // ahead of time by the caller so the first batch does not wait for memory.
-__device__ __forceinline__ uint64_t prefetch_row(const void* rp, int ow, uint64_t n_rows, uint32_t r0) {
-  const uint64_t r = (uint64_t)r0 + 1 + threadIdx.x;
-  return r < n_rows ? (uint64_t)ld_off(rp, r, ow) : ~0ull;
+// Words of row_ptr[r0 + 1 + threadIdx.x] (index clamped to n_rows; callers
+// test r < n_rows themselves), loaded without a branch on the offset width;
+// combine with row_word().
+struct RowPf {
+  uint32_t lo, hi;
+};
+__device__ __forceinline__ RowPf prefetch_row(const void* rp, int lg, uint64_t n_rows, uint32_t r0) {
+  const uint64_t r = min((uint64_t)r0 + 1 + threadIdx.x, n_rows);
+  const uint8_t* b = (const uint8_t*)rp + (r << lg);
+  return RowPf{*gm((const uint32_t*)b), *gm((const uint32_t*)(b + (lg == 3 ? 4 : 0)))};
+}
+__device__ __forceinline__ uint64_t row_word(RowPf p, int lg) {
+  return (uint64_t)p.lo | ((uint64_t)(lg == 3 ? p.hi : 0u) << 32);
 }
 
 __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t n_rows, uint64_t k0,
@@ -527,16 +537,28 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
   if (threadIdx.x == 0) *s_extra = 0;
   __syncthreads();
   const uint64_t kend = k0 + n;
-  for (uint64_t base = (uint64_t)r0 + 1;; base += kBlock) {
+  // the first kBlock rows come from the prefetched value, the rest (rows
+  // shorter than kSub / kBlock cells on average) are loaded here
+  bool more;
+  {
+    bool stop = (uint64_t)r0 + 1 + threadIdx.x >= n_rows;
+    if (!stop) {
+      if (pf >= k0 && pf < kend) atomicAdd(&incl[pf - k0], 1u);
+      else if (pf == kend) atomicAdd(s_extra, 1u);
+      stop = pf > kend;
+    }
+    more = !__syncthreads_or(stop);
+  }
+  for (uint64_t base = (uint64_t)r0 + 1 + kBlock; more; base += kBlock) {
     const uint64_t r = base + threadIdx.x;
     bool stop = r >= n_rows;
     if (!stop) {
-      const uint64_t v = base == (uint64_t)r0 + 1 ? pf : (uint64_t)ld_off(rp, r, ow);
+      const uint64_t v = (uint64_t)ld_off(rp, r, ow);
       if (v >= k0 && v < kend) atomicAdd(&incl[v - k0], 1u);
       else if (v == kend) atomicAdd(s_extra, 1u);
       stop = v > kend;
     }
-    if (__syncthreads_or(stop)) break;
+    more = !__syncthreads_or(stop);
   }
   // inclusive scan of the per-position row counts
   constexpr int kPer = kSub / kBlock;
@@ -631,12 +653,44 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
 //   pass 0:   a = column, c = low word of the payload offset; `pend` = low word
 //             of the offset after the wave's last cell, `base` = full offset of
 //             the sub-chunk's first cell
-//   pass >=1: a = column, b = size, c = row, d = cell index
+//   pass >=1: a = column, b = size, c = row, d = cell index, and (finish after
+//             a records-only pass) e, f = low and high words of the payload offset
 struct SubLoad {
-  uint32_t a[kItems], b[kItems], c[kItems], d[kItems];
+  uint32_t a[kItems], b[kItems], c[kItems], d[kItems], e[kItems], f[kItems];
   uint32_t pend;
-  uint64_t base;
+  uint32_t base_lo, base_hi;  // words of the first cell's offset (hi unused for 4-byte offsets)
 };
+// which SubLoad fields a kernel uses
+constexpr int kFieldsPass0 = 1 | 4 | 32;
+constexpr int kFieldsRec = 1 | 2 | 4 | 8;
+constexpr int kFieldsRecSo = kFieldsRec | 16 | 64;
+
+// Hands a prefetch to the next iteration. The empty asm statements read each
+// value, so the wait for those loads lands here, inside the iteration that
+// issued them, where the compiler counts the younger memory operations
+// exactly; carried through the loop edge as pending loads, their first use
+// would be given a conservative (full) wait instead.
+__device__ __forceinline__ uint32_t settled(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+template <int kFields>
+__device__ __forceinline__ void settle(SubLoad& dst, const SubLoad& src) {
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    if (kFields & 1) dst.a[r] = settled(src.a[r]);
+    if (kFields & 2) dst.b[r] = settled(src.b[r]);
+    if (kFields & 4) dst.c[r] = settled(src.c[r]);
+    if (kFields & 8) dst.d[r] = settled(src.d[r]);
+    if (kFields & 16) dst.e[r] = settled(src.e[r]);
+    if (kFields & 64) dst.f[r] = settled(src.f[r]);
+  }
+  if (kFields & 32) {
+    dst.pend = settled(src.pend);
+    dst.base_lo = settled(src.base_lo);
+    dst.base_hi = settled(src.base_hi);
+  }
+}
 
 __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, const void* poff,
                                                uint64_t kfirst, uint32_t n, int lg) {
@@ -648,11 +702,13 @@ __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, c
     S.c[r] = ld_lo(poff, kfirst + min(i, n), lg);  // the offset array has one more entry
   }
   S.pend = ld_lo(poff, kfirst + min(w * kWaveCells + kWaveCells, n), lg);
-  S.base = ld_full(poff, kfirst, lg);
+  const uint8_t* b = (const uint8_t*)poff + (kfirst << lg);
+  S.base_lo = *gm((const uint32_t*)b);
+  S.base_hi = *gm((const uint32_t*)(b + (lg == 3 ? 4 : 0)));
 }
 
 __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
-                                             uint64_t pos0, uint32_t n) {
+                                             const uint64_t* so, uint64_t pos0, uint32_t n) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
@@ -660,6 +716,11 @@ __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const 
     const uint2 x = ks[pos0 + i];
     const uint2 y = rk[pos0 + i];
     S.a[r] = x.x; S.b[r] = x.y; S.c[r] = y.x; S.d[r] = y.y;
+    if (so) {
+      const uint64_t v = gm(so)[pos0 + i];
+      S.e[r] = (uint32_t)v;
+      S.f[r] = (uint32_t)(v >> 32);
+    }
   }
 }
 
@@ -678,6 +739,10 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
   }
 }
 
+// One instance per kind of pass, so the loop has no branch between the two
+// load layouts: a branch there makes the compiler reconcile the registers of
+// in-flight loads at the join, which waits for them.
+template <bool kPass0, bool kDefer>
 __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   __shared__ SortLds L;
   __shared__ uint32_t s_rc[kMaxFanout];  // running destination cell per digit (segment relative)
@@ -709,7 +774,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   const uint64_t hb = a.hstart[si];
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
-  const bool pass0 = a.pass == 0;
+  constexpr bool pass0 = kPass0;
+  constexpr int kFields = kPass0 ? kFieldsPass0 : kFieldsRec;
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
   const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
   // item fields used in the loop, read once
@@ -728,10 +794,11 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
   }
   uint32_t r0 = 0;
-  uint64_t rpf = 0;
-  if (pass0) {
+  RowPf rpf{0, 0}, rpf_next{0, 0};
+  if constexpr (pass0) {
     r0 = coop_row_search(i_rp, ow, i_nrows, kbase + c_begin);
-    rpf = prefetch_row(i_rp, ow, i_nrows, r0);
+    rpf_next = prefetch_row(i_rp, lg, i_nrows, r0);
+    rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
   }
   __syncthreads();
   uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
@@ -740,25 +807,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if (pass0) load_sub_pass0(cur, i_col, i_poff, kbase + c_begin, n0, lg);
-    else load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0 + c_begin, n0);
+    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg);
+    else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c_begin, n0);
+    settle<kFields>(cur, nxt);  // the loop's first iteration then starts from settled registers too
   }
   for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
     const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
     const uint64_t c1 = c0 + kSub;
-    if (c1 < c_end) {  // next sub-chunk's loads go out now
-      const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg);
-      else load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, n1);
-    }
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
     uint64_t sub_base;
     uint32_t first_row = 0, last_row = 0;
-    if (pass0) {
+    if constexpr (pass0) {
       const uint64_t kf = kbase + c0;
-      sub_base = cur.base;
-      const uint32_t r_next = expand_rows(i_rp, ow, i_nrows, kf, n, r0, rpf, L.bpre, &s_extra, s_red);
-      rpf = prefetch_row(i_rp, ow, i_nrows, r_next);  // next sub-chunk's rows
+      sub_base = (uint64_t)cur.base_lo | ((uint64_t)(lg == 3 ? cur.base_hi : 0u) << 32);
+      const uint32_t r_next = expand_rows(i_rp, ow, i_nrows, kf, n, r0, row_word(rpf, lg), L.bpre,
+                                          &s_extra, s_red);
+      rpf_next = prefetch_row(i_rp, lg, i_nrows, r_next);  // next sub-chunk's rows
       sizes_from_offsets(cur, sz);
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
@@ -786,6 +850,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
       dg[r] = i < n ? digit_of(key[r], sg, s_lb, R) : 0u;
     }
+    // The next sub-chunk's loads go out once this one's registers have been
+    // read (the wait counter is in order, so a use of the current loads after
+    // issuing these would wait for these too) and fly during the sort.
+    if (c1 < c_end) {
+      const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
+      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg);
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
+    }
     sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
 
     const uint8_t* src_base = pass0 ? i_pay + sub_base : a.pay_in + sub_base;
@@ -795,11 +867,26 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       src_part = owner_of(s_lb, R, (int64_t)first_row);
       xfer_per_cell = owner_of(s_lb, R, (int64_t)last_row) != src_part;
     }
+    if constexpr (kDefer) {
+      // records only: each cell's payload stays where it is in the input
+      // level buffer, and its byte offset there goes with the record
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = r * kBlock + threadIdx.x;
+        if (i < n) {
+          const uint32_t d = L.dig[i];
+          const uint64_t cd = seg_out + s_rc[d] + (i - L.wc[d * kNW]);
+          a.ks_out[cd] = make_uint2(L.key[i], L.sz[i]);
+          a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+          gm(a.so_out)[cd] = sub_base + L.src[i];
+        }
+      }
+    }
     // write the sorted cells at their digit's running destination, kPay
     // cells per lane at a time: payload loads first, then the records, then
     // the payload stores
 #pragma unroll
-    for (int g = 0; g < kItems; g += kPay) {
+    for (int g = 0; g < (kDefer ? 0 : kItems); g += kPay) {
       uint8_t* pd[kPay];
       const uint8_t* ps[kPay];
       uint32_t pz[kPay];
@@ -861,13 +948,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       s_rb[d] += L.bpre[i1] - L.bpre[i0];
     }
     __syncthreads();
-    cur = nxt;
+    settle<kFields>(cur, nxt);
+    if constexpr (pass0) rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
   }
 }
 
 // ----------------------------------------------------------------------------- finish
 
+// kGather: the last pass moved records only; each cell's payload is read
+// from the previous level buffer at the bucket's src0 plus the cell's stored
+// offset. Otherwise payloads follow the records in the same level buffer.
+template <bool kGather>
 __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
+  constexpr int kFields = kGather ? kFieldsRecSo : kFieldsRec;
+  const uint64_t* const so = kGather ? a.so_in : nullptr;
   __shared__ SortLds L;
   __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
   __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
@@ -941,11 +1035,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 
   uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
   SubLoad cur, nxt;
-  if (len) load_sub_rec(cur, a.ks_in, a.rk_in, sg.cell0, min((uint32_t)kSub, len));
+  if (len) {
+    load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0, min((uint32_t)kSub, len));
+    settle<kFields>(cur, nxt);
+  }
   for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
     const uint32_t n = min((uint32_t)kSub, len - c0);
     const uint32_t c1 = c0 + kSub;
-    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -954,14 +1050,27 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       const uint32_t d = key[r] - sg.key_lo;
       dg[r] = i < n ? (d < nc ? d : nc - 1) : 0u;
     }
-    const uint32_t subtot = sub_src_prefix(sz, src, s_red);
+    uint32_t subtot = 0;
+    if constexpr (kGather) {
+      // the column is not needed after the sort here, so its LDS slot carries
+      // the high word of the payload offset through it
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        src[r] = cur.e[r];
+        key[r] = cur.f[r];
+      }
+    } else {
+      subtot = sub_src_prefix(sz, src, s_red);
+    }
+    // next sub-chunk's loads, issued after this one's registers were read
+    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
     sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
     if (!multi) {
       // one sub-chunk: its digit scan is the column layout of the whole bucket
       for (uint32_t c = threadIdx.x; c < nc; c += kBlock)
         st_off(t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kNW]), ow);
     }
-    const uint8_t* src_base = a.pay_in + src_sub;
+    const uint8_t* src_base = a.pay_in + (kGather ? 0 : src_sub);
 #pragma unroll
     for (int g = 0; g < kItems; g += kPay) {
       uint8_t* pd[kPay];
@@ -988,7 +1097,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
           }
           pz[q] = L.sz[i];
           pd[q] = o_pay + pb[q];
-          ps[q] = src_base + L.src[i];
+          ps[q] = src_base + (kGather ? ((uint64_t)L.key[i] << 32 | L.src[i]) : (uint64_t)L.src[i]);
         }
       }
       PayRegs P;
@@ -1015,7 +1124,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       __syncthreads();
     }
     src_sub += subtot;
-    cur = nxt;
+    settle<kFields>(cur, nxt);
     if (len == 0) break;
   }
 }
@@ -1181,7 +1290,11 @@ hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
-  if (a.g8) hipLaunchKernelGGL(k_pass_scatter, grid1(a.g8), dim3(kBlock), 0, s, a);
+  if (a.g8) {
+    if (a.pass == 0) hipLaunchKernelGGL((k_pass_scatter<true, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    else if (a.so_out) hipLaunchKernelGGL((k_pass_scatter<false, true>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_pass_scatter<false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -1191,7 +1304,10 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
-  if (a.nbuckets) hipLaunchKernelGGL(k_finish, grid1(a.g8), dim3(kBlock), 0, s, a);
+  if (a.nbuckets) {
+    if (a.so_in) hipLaunchKernelGGL(k_finish<true>, grid1(a.g8), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL(k_finish<false>, grid1(a.g8), dim3(kBlock), 0, s, a);
+  }
   return hipGetLastError();
 }
 

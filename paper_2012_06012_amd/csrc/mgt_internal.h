@@ -18,6 +18,13 @@
 //               stable counting sort by column that writes the outputs and
 //               copies every payload to its final place.
 //
+// Payload bytes move in every pass but the last. With two or more passes the
+// last one moves records only and stores, per cell, where its payload sits in
+// the previous level buffer (a byte offset); the finish then copies each
+// payload from there. A finish bucket's cells all come from one segment of
+// that level, whose bytes are a contiguous range, and the buckets run in
+// column order, so those reads stay inside a few segments at a time.
+//
 // Positions: level buffers hold all items back to back; an item's cells
 // keep, at every level, the range [cell_base, cell_base + nnz) and a segment's
 // range is exactly where its cells sit in the final output. Byte ranges work

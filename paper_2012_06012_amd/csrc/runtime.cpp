@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -44,14 +45,31 @@ struct Sched {
   int finish_bits = 0;
 };
 
-// Number of passes needed for `B` bits when the first pass may take `first_cap`.
-int passes_for(int B, int first_cap) {
+// Schedule caps from the environment: MGT_MAX_PASS_BITS (1..8) bounds the bits
+// of a bits-mode pass and MGT_MAX_FINISH_BITS (0..10) the column bits of a
+// finish bucket. Lower caps trade more passes for smaller fan-outs; tests use
+// them to reach three- and four-pass schedules on small inputs.
+int env_cap(const char* name, int lo, int hi, int dflt) {
+  const char* e = std::getenv(name);
+  if (e && *e) {
+    const int v = std::atoi(e);
+    if (v >= lo && v <= hi) return v;
+  }
+  return dflt;
+}
+int max_pass_bits() { return env_cap("MGT_MAX_PASS_BITS", 1, kMaxBitsPerPass, kMaxBitsPerPass); }
+int max_finish_bits() { return env_cap("MGT_MAX_FINISH_BITS", 0, kMaxFinishBits, kMaxFinishBits); }
+
+// Number of passes needed for `B` bits when the first pass may take `first_cap`
+// and every later one `mb`.
+int passes_for(int B, int first_cap, int mb) {
   if (B <= 0) return 1;
   int rest = B - std::min(B, first_cap);
-  return 1 + (rest + kMaxBitsPerPass - 1) / kMaxBitsPerPass;
+  return 1 + (rest + mb - 1) / mb;
 }
 
-Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned) {
+Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
+                    int mb, int mf) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -67,16 +85,16 @@ Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, 
     const double per_col = (double)nnz / (double)n_cols;
     fb_ideal = floor_log2_u64((uint64_t)std::max(1.0, 2.0 * kSub / per_col));
   } else {
-    fb_ideal = kMaxFinishBits;
+    fb_ideal = mf;
   }
-  fb_ideal = std::min(std::max(fb_ideal, 0), std::min(kMaxFinishBits, K));
+  fb_ideal = std::min(std::max(fb_ideal, 0), std::min(mf, K));
   const int first_cap = partitioned
-      ? (R <= (int32_t)kMaxPartFanout ? floor_log2_u64(kMaxPartFanout / (uint32_t)R) : 0)
-      : kMaxBitsPerPass;
+      ? std::min(mb, R <= (int32_t)kMaxPartFanout ? floor_log2_u64(kMaxPartFanout / (uint32_t)R) : 0)
+      : mb;
   // Fewest passes first, then the smallest finish width that achieves them.
   int best_fb = fb_ideal, best_L = 1 << 30;
-  for (int fb = fb_ideal; fb <= std::min(kMaxFinishBits, K); ++fb) {
-    const int L = passes_for(K - fb, first_cap);
+  for (int fb = fb_ideal; fb <= std::min(mf, K); ++fb) {
+    const int L = passes_for(K - fb, first_cap, mb);
     if (L < best_L) { best_L = L; best_fb = fb; }
   }
   if (K <= fb_ideal) { best_fb = K; best_L = 1; }
@@ -92,6 +110,13 @@ Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, 
     s.bits[l] = (rest + left - 1) / left;
     rest -= s.bits[l];
   }
+  return s;
+}
+
+Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned) {
+  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, max_pass_bits(), max_finish_bits());
+  if (s.n_levels > kMaxLevels)
+    s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, kMaxBitsPerPass, kMaxFinishBits);
   return s;
 }
 
@@ -120,7 +145,7 @@ struct Layout {
   uint64_t o_segs[kMaxLevels + 1], o_tcnt[kMaxLevels], o_hsz[kMaxLevels], o_tstart[kMaxLevels],
       o_hstart[kMaxLevels];
   uint64_t o_hcnt, o_hbyt, o_ocnt, o_obyt, o_ttot, o_tsrc, o_scan;
-  uint64_t o_ks[2], o_rk[2], o_pay[2];
+  uint64_t o_ks[2], o_rk[2], o_pay[2], o_so = 0;
   uint64_t bytes = 0;
 };
 
@@ -200,18 +225,23 @@ Layout make_layout(std::vector<HostItem>& items) {
   y.o_ttot = take(4ull * y.tiles_all_max);
   y.o_tsrc = take(8ull * (y.tiles_all_max + 1));
   y.o_scan = take(scan_scratch_bytes(y.scan_max));
+  // Records ping-pong between two level buffers. Payload bytes are written
+  // by every pass but the last when there are two or more passes (the last
+  // one records an 8-byte payload offset per cell instead), so a second
+  // payload buffer is needed only from three passes on.
   const int nbuf = L >= 2 ? 2 : 1;
+  const int npay = L >= 3 ? 2 : 1;
   for (int b = 0; b < 2; ++b) {
     if (b < nbuf) {
       y.o_ks[b] = take(8ull * y.total_nnz);
       y.o_rk[b] = take(8ull * y.total_nnz);
-      y.o_pay[b] = take(y.total_bytes + 16);
     } else {
       y.o_ks[b] = y.o_ks[0];
       y.o_rk[b] = y.o_rk[0];
-      y.o_pay[b] = y.o_pay[0];
     }
+    y.o_pay[b] = b < npay ? take(y.total_bytes + 16) : y.o_pay[0];
   }
+  if (L >= 2) y.o_so = take(8ull * y.total_nnz);
   y.bytes = o + 256;
   return y;
 }
@@ -376,6 +406,8 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.ks_out = (uint2*)(W + y.o_ks[bo2]);
     a.rk_out = (uint2*)(W + y.o_rk[bo2]);
     a.pay_out = (uint8_t*)(W + y.o_pay[bo2]);
+    a.so_out = (L >= 2 && l == L - 1) ? (uint64_t*)(W + y.o_so) : nullptr;
+    if (a.so_out) a.pay_out = nullptr;
     a.hcnt = hcnt;
     a.hbyt = hbyt;
     a.ttot = ttot;
@@ -420,7 +452,8 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   const int bl = (L - 1) & 1;
   f.ks_in = (const uint2*)(W + y.o_ks[bl]);
   f.rk_in = (const uint2*)(W + y.o_rk[bl]);
-  f.pay_in = (const uint8_t*)(W + y.o_pay[bl]);
+  f.pay_in = (const uint8_t*)(W + y.o_pay[L >= 2 ? (L - 2) & 1 : bl]);
+  f.so_in = L >= 2 ? (const uint64_t*)(W + y.o_so) : nullptr;
   f.abort_flag = d_abort;
   f.offset_width = ow;
   f.g8 = align_up(y.nseg[L], 8);

@@ -42,6 +42,21 @@ def test_plan_host_only_and_workspace_grows():
     assert 0 < p1.workspace_bytes < p2.workspace_bytes
 
 
+def test_schedule_caps_from_environment(monkeypatch):
+    # a longer schedule needs a second level buffer and the per-cell payload
+    # offsets of its last pass: the workspace grows; out-of-range caps are ignored
+    mgt = _lib()
+    args = (30000, 30000, 150000, 1500000, 8, None)
+    base = mgt.mgt_plan(*args).workspace_bytes
+    monkeypatch.setenv("MGT_MAX_PASS_BITS", "4")
+    monkeypatch.setenv("MGT_MAX_FINISH_BITS", "4")
+    longer = mgt.mgt_plan(*args).workspace_bytes
+    assert longer > base + 16 * 150000
+    monkeypatch.setenv("MGT_MAX_PASS_BITS", "0")
+    monkeypatch.setenv("MGT_MAX_FINISH_BITS", "11")
+    assert mgt.mgt_plan(*args).workspace_bytes == base
+
+
 @pytest.mark.parametrize("args,code", [
     ((-1, 10, 0, 0, 8, None), -1),                 # negative rows
     ((10, 10, 5, 0, 3, None), -1),                 # bad offset width

@@ -584,12 +584,16 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
 // Payload copies of a lane's kItems cells, split in two so the caller can
 // put other work (the record stores) between the loads and the stores. When
 // every cell is dword aligned on both sides and at most 32 bytes, the words
-// are loaded into registers up front (`fast`); otherwise the cells are copied
-// one by one in the store phase.
+// are loaded into registers up front (`fast`) as at most three pieces per
+// cell (16, 16 or 8 + 4 bytes; dword-aligned multi-dword accesses are legal
+// on gfx950), so a wave moves a cell in up to three instructions instead of
+// up to eight; otherwise the cells are copied one by one in the store phase.
 constexpr int kPay = 4;  // cells per lane whose payload words are held at once
 
+typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
 struct PayRegs {
-  uint32_t v[kPay][8];
+  u32x4a v[kPay][2];
   bool fast;
 };
 
@@ -604,10 +608,18 @@ __device__ __forceinline__ void pay_load(PayRegs& P, uint8_t* const (&dst)[kPay]
   P.fast = fast;
   if (fast) {
 #pragma unroll
-    for (int r = 0; r < kPay; ++r)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) P.v[r][j] = gm((const uint32_t*)src[r])[j];
+    for (int r = 0; r < kPay; ++r) {
+      const GMEM uint8_t* s = gm(src[r]);
+      const uint32_t z = sz[r];
+      if (z >= 16u) P.v[r][0] = *(const GMEM u32x4a*)s;
+      const uint32_t o1 = z >= 16u ? 16u : 0u, rem = z - o1;
+      if (rem >= 16u) {
+        P.v[r][1] = *(const GMEM u32x4a*)(s + 16);
+      } else {
+        if (rem >= 8u) P.v[r][1].xy = *(const GMEM u32x2a*)(s + o1);
+        if (rem & 4u) P.v[r][1].z = *(const GMEM uint32_t*)(s + o1 + (rem & 8u));
+      }
+    }
   }
 }
 
@@ -616,10 +628,18 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
                                           const uint32_t (&sz)[kPay]) {
   if (P.fast) {
 #pragma unroll
-    for (int r = 0; r < kPay; ++r)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if ((uint32_t)(4 * j) < sz[r]) gm((uint32_t*)dst[r])[j] = P.v[r][j];
+    for (int r = 0; r < kPay; ++r) {
+      GMEM uint8_t* d = gm(dst[r]);
+      const uint32_t z = sz[r];
+      if (z >= 16u) *(GMEM u32x4a*)d = P.v[r][0];
+      const uint32_t o1 = z >= 16u ? 16u : 0u, rem = z - o1;
+      if (rem >= 16u) {
+        *(GMEM u32x4a*)(d + 16) = P.v[r][1];
+      } else {
+        if (rem >= 8u) *(GMEM u32x2a*)(d + o1) = P.v[r][1].xy;
+        if (rem & 4u) *(GMEM uint32_t*)(d + o1 + (rem & 8u)) = P.v[r][1].z;
+      }
+    }
   } else {
     bool small = true;
 #pragma unroll
@@ -642,7 +662,6 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
     }
   }
 }
-
 // ----------------------------------------------------------------------------- pass: scatter
 
 // Loads of one sub-chunk, kept in registers so the next sub-chunk can be in
@@ -968,7 +987,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   __shared__ uint32_t s_red[kNW + 1];
   __shared__ uint64_t s_red64[kNW + 1];
   if (aborted(a.abort_flag)) return;
-  const uint64_t bk = xcd_tile(blockIdx.x, a.g8);
+  // Gathering finishes run their buckets in plain column order on all XCDs
+  // at once: the buckets in flight then read from one or two source segments
+  // (tens of MB, resident in the memory-side cache) instead of eight.
+  const uint64_t bk = kGather ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.g8);
   if (bk >= a.nbuckets) return;
   const Seg sg = a.buckets[bk];
   const ItemDev* it = &a.items[sg.item];

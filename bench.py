@@ -111,12 +111,13 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_bytes_each_way": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
 
 
-def _device(a, dev):
+def _device(a, dev, fixed_width=False):
     import torch
     from paper_2012_06012_amd import mgt
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)  # noqa: E731
-    return mgt.DeviceCsr(a.n_rows, a.n_cols, t(a.row_ptr), t(a.col), t(a.payload_off),
-                         t(a.payload), a.bounds, a.offset_width)
+    return mgt.DeviceCsr(a.n_rows, a.n_cols, t(a.row_ptr), t(a.col),
+                         None if fixed_width else t(a.payload_off), t(a.payload), a.bounds,
+                         a.offset_width, fixed_width)
 
 
 def bench_batch(args):
@@ -265,10 +266,11 @@ def bench_hetero(args):
     t0 = time.time()
     a = gen.hetero(seed=args.seed, scale=args.scale)
     log(f"[hetero] generated nnz={a.nnz} payload={a.payload_bytes} in {time.time() - t0:.1f}s")
-    d = _device(a, dev)
+    fixed = args.fixed_width
+    d = _device(a, dev, fixed_width=fixed)
     plan = mgt.plan_for(d)
     ws = mgt.workspace_for(plan, dev)
-    out = mgt.alloc_outputs(d, partitioned=True)
+    out = mgt.alloc_outputs(d, partitioned=True, payload_off=not fixed)
     ms = _timed(lambda: mgt.transpose(d, plan=plan, workspace=ws, partitioned=True, out=out),
                 args.steps, args.warmup)
     t_row_ptr = out["t_row_ptr"].cpu().numpy()
@@ -280,11 +282,17 @@ def bench_hetero(args):
         s = oracle.transpose_columns(a, lo, lo + 32)
         p0, p1 = int(t_row_ptr[lo]), int(t_row_ptr[lo + 32])
         ok &= bool(np.array_equal(out["t_col"][p0:p1].cpu().numpy(), s.t_col))
-        po = out["t_payload_off"][p0:p1 + 1].cpu().numpy()
+        if fixed:
+            po = np.arange(p0, p1 + 1, dtype=np.int64) * 28
+        else:
+            po = out["t_payload_off"][p0:p1 + 1].cpu().numpy()
         ok &= bool(np.array_equal(out["t_payload"][int(po[0]):int(po[-1])].cpu().numpy(),
                                   s.t_payload))
     b_alg = a.algorithmic_bytes(partitioned=True)
-    res = {"metric": "cells/s (partitioned transpose, bit-exact sampled)", "mode": "hetero",
+    if fixed:  # no payload offsets read or written
+        b_alg -= 2 * (a.nnz + 1) * a.offset_width
+    res = {"metric": "cells/s (partitioned transpose, bit-exact sampled)",
+           "mode": "hetero" + (" fixed-width" if fixed else ""),
            "value": a.nnz / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
            "hbm_frac_step": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bit_exact_sampled": ok,
            "config": {"workload": "heterogeneous multigraph 2^21 x 2^21, 2^30 cells, 28-byte "
@@ -366,6 +374,8 @@ def main():
                          "vs per-matrix launches; serve: the continuous-batching request loop vs "
                          "per-request plain launches")
     ap.add_argument("--items", type=int, default=512, help="batch / serve: matrices or requests")
+    ap.add_argument("--fixed-width", action="store_true",
+                    help="hetero: run the fixed-width mode (no payload offsets on the device)")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
@@ -423,6 +433,16 @@ def main():
     wall = time.perf_counter() - w0
     ms = ev0.elapsed_time(ev1) / args.steps
     log(f"[bench] {args.steps} steps: {ms:.3f} ms/step (wall {wall / args.steps * 1e3:.3f} ms)")
+    # spread across steps: the same number of steps again, each between its own events
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    evs[0].record(stream)
+    for i in range(args.steps):
+        step()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
+    spread = {"p50": float(np.percentile(per_step, 50)), "p99": float(np.percentile(per_step, 99)),
+              "min": float(per_step.min()), "max": float(per_step.max())}
 
     # per-stage device times (events recorded by the library on the same stream)
     tplan = mgt.plan_for(d, mgt.DEBUG_TIMING)
@@ -512,6 +532,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_spread": spread,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

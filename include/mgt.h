@@ -68,8 +68,20 @@ typedef enum {
 enum {
   MGT_VALIDATE = 1u << 0,     /* device-side data checks, result in *d_status            */
   MGT_EMIT_PERM = 1u << 1,    /* callers will pass perm: perm[p] = input cell of output p */
-  MGT_DEBUG_TIMING = 1u << 2  /* record per-stage times (mgt_plan_stage_times)           */
+  MGT_DEBUG_TIMING = 1u << 2, /* record per-stage times (mgt_plan_stage_times)           */
+  MGT_FIXED_WIDTH = 1u << 3   /* every cell carries the same number of payload bytes     */
 };
+
+/*
+ * Fixed-width cells (MGT_FIXED_WIDTH; the homogeneous-value variant of
+ * Section 2 and the identical-cell-size case remarked on in Section 3): every
+ * cell carries w = payload_bytes / nnz bytes, so cell k's payload is bytes
+ * [k*w, (k+1)*w) on both sides and no offsets need to move. payload_bytes
+ * must be a multiple of nnz (any value when nnz == 0), else MGT_EINVAL.
+ * payload_off may then be NULL (it is never read); t_payload_off may be NULL
+ * (it is then not written; when given it receives p*w as usual). For a batch
+ * the flag is taken from each item's descriptor.
+ */
 
 typedef struct mgt_plan_s* mgt_plan_t;
 
@@ -84,7 +96,8 @@ typedef struct {
   const int64_t* part_bounds; /* host, R+1 entries: 0 = b[0] <= b[1] <= ... <= b[R]
                               = n_rows; empty partitions allowed; may be NULL when
                               R == 1                                                */
-  uint32_t flags;          /* MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING      */
+  uint32_t flags;          /* MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING |
+                              MGT_FIXED_WIDTH                                       */
 } mgt_desc;
 
 /*
@@ -101,7 +114,8 @@ int mgt_plan_destroy(mgt_plan_t plan);
  *   inputs : row_ptr[n_rows+1], col[nnz], payload_off[nnz+1], payload[payload_bytes]
  *   outputs: t_row_ptr[n_cols+1], t_col[nnz], t_payload_off[nnz+1],
  *            t_payload[payload_bytes], perm[nnz] (only with MGT_EMIT_PERM, else NULL)
- * payload / t_payload may be NULL when payload_bytes == 0. Outputs must not
+ * payload / t_payload may be NULL when payload_bytes == 0; with
+ * MGT_FIXED_WIDTH payload_off and t_payload_off may be NULL. Outputs must not
  * overlap inputs. workspace: >= the size mgt_plan reported, 256-byte aligned.
  */
 int mgt_transpose(mgt_plan_t plan, const void* row_ptr, const int32_t* col,

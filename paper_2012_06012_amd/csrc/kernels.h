@@ -10,6 +10,7 @@ namespace mgt {
 // Geometry shared by host and device.
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
 constexpr int kSub = 2048;          // cells sorted in LDS at once
+constexpr int kMaxPassBits = 8;     // digit bits of a bits-mode pass (fan-out 256)
 constexpr int kScanBlock = 4096;    // elements per scan workgroup
 
 // Arguments of a partition pass (hist and scatter share them).

@@ -181,12 +181,16 @@ __global__ __launch_bounds__(kBlock) void k_validate(const ItemDev* items, int32
       if (i == n_rows && r0 != it.nnz) bad = true;
     }
     if (i <= nnz) {
-      const int64_t p0 = ld_off(it.poff, i, ow);
-      if (i == 0 && p0 != 0) bad = true;
-      if (i == nnz && p0 != it.payload_bytes) bad = true;
+      if (it.fixed_w < 0) {  // fixed-width cells have no offsets to check
+        const int64_t p0 = ld_off(it.poff, i, ow);
+        if (i == 0 && p0 != 0) bad = true;
+        if (i == nnz && p0 != it.payload_bytes) bad = true;
+        if (i < nnz) {
+          const int64_t d = ld_off(it.poff, i + 1, ow) - p0;
+          if (d < 0 || d >= ((int64_t)1 << 32)) bad = true;
+        }
+      }
       if (i < nnz) {
-        const int64_t d = ld_off(it.poff, i + 1, ow) - p0;
-        if (d < 0 || d >= ((int64_t)1 << 32)) bad = true;
         const int32_t c = it.col[i];
         if (c < 0 || (int64_t)c >= it.n_cols) bad = true;
       }
@@ -317,8 +321,28 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     const int32_t* col = it->col;
     const void* poff = it->poff;
     const int lg = ow == 8 ? 3 : 2;
+    const int32_t fw = it->fixed_w;
     // the tile's bytes exactly; below 2^32 they make every low-word size exact
-    mybytes = threadIdx.x == 0 ? ld_full(poff, kbase + c_end, lg) - ld_full(poff, kbase + c_begin, lg) : 0;
+    if (fw >= 0)
+      mybytes = threadIdx.x == 0 ? (c_end - c_begin) * (uint64_t)fw : 0;
+    else
+      mybytes = threadIdx.x == 0 ? ld_full(poff, kbase + c_end, lg) - ld_full(poff, kbase + c_begin, lg) : 0;
+    if (fw >= 0) {  // fixed-width cells: sizes are known, only the columns are read
+      for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+        uint32_t key[kBatch];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q)
+          key[q] = (uint32_t)gm(col)[kbase + min(c + (uint64_t)q * kBlock, c_end - 1)];
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) {
+          if (c + (uint64_t)q * kBlock < c_end) {
+            const uint32_t d = digit_of(key[q], sg, s_lb, R);
+            atomicAdd(&s_cnt[d], 1u);
+            atomicAdd(&s_byt[d], (uint32_t)fw);
+          }
+        }
+      }
+    } else
     for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
       uint32_t key[kBatch], p0[kBatch], p1[kBatch];
 #pragma unroll
@@ -374,23 +398,29 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 
 // ----------------------------------------------------------------------------- shared sub-chunk sort
 
-// LDS state of one stable sub-chunk sort.
-struct SortLds {
+// LDS state of one stable sub-chunk sort, for up to kFan digits. kBytes: the
+// sorted byte prefix (bpre) is kept, for passes that place payload bytes.
+template <int kFan, bool kBytes>
+struct SortLdsT {
+  static constexpr bool has_bytes = kBytes;
   uint32_t key[kSub];
   uint32_t sz[kSub];
   uint32_t row[kSub];
   uint32_t idx[kSub];
   uint32_t src[kSub];       // payload offset relative to the sub-chunk's first byte
-  uint32_t bpre[kSub + 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
+  uint32_t bpre[kBytes ? kSub + 1 : 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
   uint16_t dig[kSub];
-  uint16_t wc[kMaxFanout * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
+  uint16_t wc[kFan * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
 };
+using SortLds = SortLdsT<kMaxFanout, true>;
+constexpr int kFanBits = 1 << kMaxPassBits;  // fan-out of a bits-mode pass
 
 // Ranks each lane's cells stably by digit (ballot multisplit per 64-cell
 // round, counters per (digit, wave)), scans the counters digit-major and
 // stores the cells in sorted order. Registers hold kItems cells per lane in
 // wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
-__device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint32_t n,
+template <class LT>
+__device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t n,
                                          const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
                                          const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
                                          const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems]) {
@@ -443,7 +473,7 @@ __device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint
     }
   }
   __syncthreads();
-  {
+  if constexpr (LT::has_bytes) {
     constexpr int kPer = kSub / kBlock;
     const uint32_t p0 = threadIdx.x * kPer;
     uint32_t v[kPer];
@@ -462,8 +492,8 @@ __device__ __forceinline__ void sort_sub(SortLds& L, uint32_t F, int dbits, uint
       ex += v[q];
     }
     if (threadIdx.x == 0) L.bpre[n] = tot;
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // Exclusive prefix (in cell order i = wave*kWaveCells + r*64 + lane) of the
@@ -711,19 +741,38 @@ __device__ __forceinline__ void settle(SubLoad& dst, const SubLoad& src) {
   }
 }
 
+// fw >= 0: fixed-width cells; their offsets are k * fw and nothing is loaded
+// for them.
 __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, const void* poff,
-                                               uint64_t kfirst, uint32_t n, int lg) {
+                                               uint64_t kfirst, uint32_t n, int lg, int32_t fw) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
     S.a[r] = (uint32_t)gm(col)[kfirst + min(i, n - 1)];
-    S.c[r] = ld_lo(poff, kfirst + min(i, n), lg);  // the offset array has one more entry
   }
-  S.pend = ld_lo(poff, kfirst + min(w * kWaveCells + kWaveCells, n), lg);
-  const uint8_t* b = (const uint8_t*)poff + (kfirst << lg);
-  S.base_lo = *gm((const uint32_t*)b);
-  S.base_hi = *gm((const uint32_t*)(b + (lg == 3 ? 4 : 0)));
+  const uint64_t kend = kfirst + min(w * kWaveCells + kWaveCells, n);
+  if (fw >= 0) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      S.c[r] = (uint32_t)((kfirst + min(i, n)) * (uint64_t)fw);
+    }
+    S.pend = (uint32_t)(kend * (uint64_t)fw);
+    const uint64_t b = kfirst * (uint64_t)fw;
+    S.base_lo = (uint32_t)b;
+    S.base_hi = (uint32_t)(b >> 32);
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = w * kWaveCells + r * kWave + lane;
+      S.c[r] = ld_lo(poff, kfirst + min(i, n), lg);  // the offset array has one more entry
+    }
+    S.pend = ld_lo(poff, kend, lg);
+    const uint8_t* b = (const uint8_t*)poff + (kfirst << lg);
+    S.base_lo = *gm((const uint32_t*)b);
+    S.base_hi = *gm((const uint32_t*)(b + (lg == 3 ? 4 : 0)));
+  }
 }
 
 __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
@@ -761,12 +810,16 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
 // One instance per kind of pass, so the loop has no branch between the two
 // load layouts: a branch there makes the compiler reconcile the registers of
 // in-flight loads at the join, which waits for them.
+// The records-only pass keeps no byte prefix and no byte cursors, and only a
+// bits-mode fan-out: under 53 KB of LDS and 168 VGPRs, so three workgroups fit
+// on a CU instead of two.
 template <bool kPass0, bool kDefer>
-__global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
-  __shared__ SortLds L;
-  __shared__ uint32_t s_rc[kMaxFanout];  // running destination cell per digit (segment relative)
-  __shared__ uint64_t s_rb[kMaxFanout];  // running destination byte per digit
-  __shared__ int32_t s_lb[kMaxParts + 1];
+__global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArgs a) {
+  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
+  __shared__ SortLdsT<kFan, !kDefer> L;
+  __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
+  __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
+  __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
   __shared__ Seg s_seg;
   __shared__ uint32_t s_si, s_extra;
   __shared__ uint32_t s_red[kNW + 1];
@@ -803,14 +856,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   const void* const i_rp = it->row_ptr;
   const uint64_t i_nrows = (uint64_t)it->n_rows;
   const uint8_t* const i_pay = it->payload;
-  const int lg = ow == 8 ? 3 : 2;
+  const int32_t i_fw = it->fixed_w;
+  const int lg = ow == 8 ? 3 : 2;  // (4-byte offsets keep every payload below 2^31 bytes)
   const uint64_t seg_out = sg.cell0;  // a segment's children share its cell range
 
-  if (sg.mode)
-    for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
+  if constexpr (kPass0)
+    if (sg.mode)
+      for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
   for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
     s_rc[d] = (uint32_t)(a.ocnt[hb + (uint64_t)d * nt + j] - seg_out);
-    s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
+    if constexpr (!kDefer) s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
   }
   uint32_t r0 = 0;
   RowPf rpf{0, 0}, rpf_next{0, 0};
@@ -826,7 +881,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg);
+    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw);
     else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c_begin, n0);
     settle<kFields>(cur, nxt);  // the loop's first iteration then starts from settled registers too
   }
@@ -874,7 +929,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     // issuing these would wait for these too) and fly during the sort.
     if (c1 < c_end) {
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg);
+      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
     }
     sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
@@ -904,8 +959,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
     // write the sorted cells at their digit's running destination, kPay
     // cells per lane at a time: payload loads first, then the records, then
     // the payload stores
+    if constexpr (!kDefer) {
 #pragma unroll
-    for (int g = 0; g < (kDefer ? 0 : kItems); g += kPay) {
+    for (int g = 0; g < kItems; g += kPay) {
       uint8_t* pd[kPay];
       const uint8_t* ps[kPay];
       uint32_t pz[kPay];
@@ -946,6 +1002,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       }
       pay_store(P, pd, ps, pz);
     }
+    }
     if (track_xfer && !xfer_per_cell) {
       const uint32_t sub = 1u << sg.bits;
       for (uint32_t p = threadIdx.x; p < R; p += kBlock) {
@@ -964,7 +1021,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_pass_scatter(PassArgs a) {
       const uint32_t i0 = L.wc[d * kNW];
       const uint32_t i1 = d + 1 < F ? L.wc[(d + 1) * kNW] : n;
       s_rc[d] += i1 - i0;
-      s_rb[d] += L.bpre[i1] - L.bpre[i0];
+      if constexpr (!kDefer) s_rb[d] += L.bpre[i1] - L.bpre[i0];
     }
     __syncthreads();
     settle<kFields>(cur, nxt);
@@ -1130,7 +1187,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
         if (i < n) {
           gm(o_col)[pp[q]] = (int32_t)L.row[i];
           if (o_perm) gm(o_perm)[pp[q]] = L.idx[i];
-          st_off(o_poff, pp[q], (int64_t)pb[q], ow);
+          if (o_poff) st_off(o_poff, pp[q], (int64_t)pb[q], ow);
         }
       }
       pay_store(P, pd, ps, pz);
@@ -1221,7 +1278,7 @@ __global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int3
   const ItemDev& it = items[blockIdx.x];
   if (threadIdx.x == 0) {
     st_off(it.t_row_ptr, (uint64_t)it.n_cols, it.nnz, ow);
-    st_off(it.t_poff, (uint64_t)it.nnz, it.payload_bytes, ow);
+    if (it.t_poff) st_off(it.t_poff, (uint64_t)it.nnz, it.payload_bytes, ow);
   }
   if (!it.part_mode || !it.xfer_cells) return;
   const uint32_t R = (uint32_t)it.n_parts;

@@ -69,7 +69,8 @@ struct ItemDev {
   int32_t key_bits;           // column bits (plain) / bits of the widest partition
   int32_t part_mode;          // 1: pass 1 splits by destination partition
   int32_t status_index;       // where this item's status word lives
-  int32_t pad;
+  int32_t fixed_w;            // payload bytes of every cell when all cells have the same
+                              // width (offset arrays unused), else -1
 };
 
 // A contiguous cell range that covers the column interval [key_lo, key_hi).

@@ -19,7 +19,7 @@ using namespace mgt;
 namespace {
 
 constexpr uint32_t kTileCells = 16384;    // cells per partition-pass tile (multiple of kSub)
-constexpr int kMaxBitsPerPass = 8;        // fan-out 256 per bits-mode pass
+constexpr int kMaxBitsPerPass = kMaxPassBits;  // fan-out 256 per bits-mode pass
 constexpr uint32_t kMaxPartFanout = 512;  // preferred fan-out of the partition pass
 constexpr int kMaxItems = 65535;
 static_assert(kTileCells % kSub == 0, "tile geometry");
@@ -255,6 +255,10 @@ int check_desc(const mgt_desc* d, bool need_bounds) {
   if (d->offset_width == 4 && (d->nnz >= (1ll << 31) || d->payload_bytes >= (1ll << 31)))
     return MGT_EUNSUPPORTED;
   if (d->nnz > 0 && (d->n_rows == 0 || d->n_cols == 0)) return MGT_EINVAL;
+  if ((d->flags & MGT_FIXED_WIDTH) && d->nnz > 0) {
+    if (d->payload_bytes % d->nnz != 0) return MGT_EINVAL;
+    if (d->payload_bytes / d->nnz >= (1ll << 31)) return MGT_EUNSUPPORTED;
+  }
   if (d->n_parts < 1 || d->n_parts > kMaxParts) return MGT_EINVAL;
   if (d->n_parts > 1 || need_bounds) {
     if (!d->part_bounds) return MGT_EINVAL;
@@ -354,6 +358,9 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     d.key_bits = it.s.key_bits;
     d.part_mode = it.s.part_mode;
     d.status_index = (int32_t)i;
+    d.fixed_w = (it.d.flags & MGT_FIXED_WIDTH)
+                    ? (int32_t)(it.d.nnz > 0 ? it.d.payload_bytes / it.d.nnz : 0)
+                    : -1;
     d.bounds = (const int64_t*)(W + y.o_bounds) + bo;
     for (int32_t r = 0; r <= it.d.n_parts; ++r)
       hb[bo + r] = (it.d.n_parts == 1 && !it.bounds) ? (r ? it.d.n_rows : 0) : it.bounds[r];
@@ -484,7 +491,9 @@ int check_io(const mgt_desc& d, uint32_t flags, const void* row_ptr, const int32
              const void* payload_off, const uint8_t* payload, const void* t_row_ptr,
              const int32_t* t_col, const void* t_payload_off, const uint8_t* t_payload,
              const uint32_t* perm) {
-  if (!row_ptr || !payload_off || !t_row_ptr || !t_payload_off) return MGT_EINVAL;
+  const bool fixed = (d.flags & MGT_FIXED_WIDTH) != 0;
+  if (!row_ptr || !t_row_ptr) return MGT_EINVAL;
+  if (!fixed && (!payload_off || !t_payload_off)) return MGT_EINVAL;
   if (d.nnz > 0 && (!col || !t_col)) return MGT_EINVAL;
   if (d.payload_bytes > 0 && (!payload || !t_payload)) return MGT_EINVAL;
   const bool want_perm = (flags & MGT_EMIT_PERM) != 0;
@@ -590,7 +599,8 @@ int mgt_plan(const mgt_desc* desc, mgt_plan_t* out, size_t* workspace_bytes) {
   if (!out) return MGT_EINVAL;
   int st = check_desc(desc, false);
   if (st != MGT_OK) return st;
-  if ((desc->flags & ~(uint32_t)(MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING)) != 0) return MGT_EINVAL;
+  if ((desc->flags & ~(uint32_t)(MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING | MGT_FIXED_WIDTH)) != 0)
+    return MGT_EINVAL;
   mgt_plan_s* p = new (std::nothrow) mgt_plan_s();
   if (!p) return MGT_ENOMEM;
   p->desc = *desc;

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgt.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED, ECANCELED = 0, -1, -2, -3, -4, -5, -6
-VALIDATE, EMIT_PERM, DEBUG_TIMING = 1, 2, 4
+VALIDATE, EMIT_PERM, DEBUG_TIMING, FIXED_WIDTH = 1, 2, 4, 8
 _NAMES = {0: "MGT_OK", -1: "MGT_EINVAL", -2: "MGT_ERANGE", -3: "MGT_ENOMEM", -4: "MGT_EHIP",
           -5: "MGT_EUNSUPPORTED", -6: "MGT_ECANCELED"}
 
@@ -218,10 +218,11 @@ class DeviceCsr:
     n_cols: int
     row_ptr: torch.Tensor
     col: torch.Tensor
-    payload_off: torch.Tensor
+    payload_off: Optional[torch.Tensor]   # may be None when fixed_width
     payload: torch.Tensor
     bounds: np.ndarray
     offset_width: int
+    fixed_width: bool = False             # every cell carries payload_bytes / nnz bytes
 
     @property
     def nnz(self) -> int:
@@ -236,13 +237,17 @@ class DeviceCsr:
         return int(len(self.bounds)) - 1
 
 
-def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, device=None):
+def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, device=None,
+                  payload_off: bool = True):
+    """Output tensors for `a`. payload_off=False leaves out t_payload_off (only
+    for fixed-width matrices, whose payload offsets are implied)."""
     dev = device or a.col.device
     odt = torch.int32 if a.offset_width == 4 else torch.int64
     out = dict(
         t_row_ptr=torch.empty(a.n_cols + 1, dtype=odt, device=dev),
         t_col=torch.empty(a.nnz, dtype=torch.int32, device=dev),
-        t_payload_off=torch.empty(a.nnz + 1, dtype=odt, device=dev),
+        t_payload_off=(torch.empty(a.nnz + 1, dtype=odt, device=dev)
+                       if payload_off or not a.fixed_width else None),
         t_payload=torch.empty(a.payload_bytes, dtype=torch.uint8, device=dev),
         perm=torch.empty(a.nnz, dtype=torch.int32, device=dev) if perm else None,
     )
@@ -259,7 +264,8 @@ def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, d
 
 def plan_for(a: DeviceCsr, flags: int = 0) -> Plan:
     return mgt_plan(a.n_rows, a.n_cols, a.nnz, a.payload_bytes, a.offset_width,
-                    a.bounds if a.n_parts >= 1 else None, flags)
+                    a.bounds if a.n_parts >= 1 else None,
+                    flags | (FIXED_WIDTH if a.fixed_width else 0))
 
 
 def workspace_for(plan: Plan, device) -> torch.Tensor:
@@ -276,7 +282,7 @@ def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: b
     """
     flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
     if plan is None:
-        plan = plan_for(a, flags)
+        plan = plan_for(a, flags)  # adds FIXED_WIDTH for fixed-width matrices
     dev = a.col.device
     if workspace is None:
         workspace = workspace_for(plan, dev)
@@ -305,7 +311,7 @@ def batch_entries(mats: Sequence[DeviceCsr], outs: Sequence[dict], perm: bool = 
         b = np.ascontiguousarray(a.bounds, dtype=np.int64)
         keep.append(b)
         d = Desc(a.n_rows, a.n_cols, a.nnz, a.payload_bytes, a.offset_width, a.n_parts,
-                 b.ctypes.data, flags)
+                 b.ctypes.data, flags | (FIXED_WIDTH if a.fixed_width else 0))
         e = dict(desc=d, row_ptr=a.row_ptr, col=a.col, payload_off=a.payload_off,
                  payload=a.payload, **{k: o.get(k) for k in (
                      "t_row_ptr", "t_col", "t_payload_off", "t_payload", "perm", "xfer_cells",

@@ -9,11 +9,17 @@ import oracle
 from workloads.gen import Csr
 
 
-def to_device(a: Csr, device="cuda"):
+def to_device(a: Csr, device="cuda", fixed_width=False):
+    """Device copy of `a`. fixed_width: every cell has the same width, and the
+    payload offsets are left on the host (the library must not need them)."""
     from paper_2012_06012_amd import mgt
     t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(device)  # noqa: E731
-    return mgt.DeviceCsr(a.n_rows, a.n_cols, t(a.row_ptr), t(a.col), t(a.payload_off),
-                         t(a.payload), np.asarray(a.bounds, np.int64), a.offset_width)
+    if fixed_width:
+        w = np.diff(a.payload_off)
+        assert w.size == 0 or (w == w[0]).all(), "cells of unequal width"
+    return mgt.DeviceCsr(a.n_rows, a.n_cols, t(a.row_ptr), t(a.col),
+                         None if fixed_width else t(a.payload_off), t(a.payload),
+                         np.asarray(a.bounds, np.int64), a.offset_width, fixed_width)
 
 
 def host(out: dict) -> dict:

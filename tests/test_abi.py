@@ -108,6 +108,33 @@ def test_transpose_rejects_null_pointers_before_launch():
     assert rc == -3
 
 
+def test_fixed_width_descriptor_and_offset_pointers():
+    mgt = _lib()
+    # payload bytes must split evenly over the cells; any size when there are none
+    with pytest.raises(mgt.MgtError) as e:
+        mgt.mgt_plan(10, 10, 4, 10, 8, None, mgt.FIXED_WIDTH)
+    assert e.value.code == -1
+    mgt.mgt_plan(10, 10, 0, 0, 8, None, mgt.FIXED_WIDTH)
+    assert mgt.mgt_plan(10, 10, 4, 12, 8, None, mgt.FIXED_WIDTH).workspace_bytes > 0
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    lib.mgt_transpose.argtypes = [ctypes.c_void_p] * 10 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                          ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)
+    # without the flag the offset arrays are required ...
+    p = mgt.mgt_plan(10, 10, 4, 12, 8, None)
+    rc = lib.mgt_transpose(p.handle, fake, fake, None, fake, fake, fake, fake, fake, None, fake,
+                           1 << 20, None, None)
+    assert rc == -1
+    rc = lib.mgt_transpose(p.handle, fake, fake, fake, fake, fake, fake, None, fake, None, fake,
+                           1 << 20, None, None)
+    assert rc == -1
+    # ... with it both may be NULL (a too-small workspace is then the first error)
+    p = mgt.mgt_plan(10, 10, 4, 12, 8, None, mgt.FIXED_WIDTH)
+    rc = lib.mgt_transpose(p.handle, fake, fake, None, fake, fake, fake, None, fake, None, fake,
+                           16, None, None)
+    assert rc == -3
+
+
 def test_partitioned_rejects_missing_outputs():
     mgt = _lib()
     p = mgt.mgt_plan(10, 10, 5, 0, 8, [0, 5, 10])

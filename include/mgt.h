@@ -150,6 +150,54 @@ int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_
 
 /* ------------------------------------------------------------------ batches */
 
+/*
+ * The two halves of the distributed transpose on their own (Section 3:
+ * Transpose = LocalTranspose . ViewSwap = ViewSwap . LocalTranspose), for a
+ * matrix X (n_rows x n_cols) with R partitions given by part_bounds, which
+ * split both axes (so R > 1 needs a square matrix). X is held in one of two
+ * views (Fig. 1):
+ *   MGT_ROW_VIEW     partition r holds X's rows [b_r, b_r+1): X's CSR,
+ *                    row_ptr[n_rows + 1];
+ *   MGT_COLUMN_VIEW  partition s holds X's columns [b_s, b_s+1) for every
+ *                    row, as a CSR over all n_rows rows; the R partitions are
+ *                    stored one after another, so row_ptr has R * n_rows + 1
+ *                    entries and (virtual) row s * n_rows + i is row i of
+ *                    partition s.
+ * Column ids are X's own in both views. Cells keep their input order inside a
+ * row.
+ *   MGT_LOCAL_TRANSPOSE  every partition transposes its own block: a row view
+ *       of X gives a column view of X^T (o_row_ptr[R * n_cols + 1]; partition
+ *       r holds the transpose of X's rows in partition r); a column view of X
+ *       gives a row view of X^T (o_row_ptr[n_cols + 1]). Output column ids are
+ *       X's row ids.
+ *   MGT_VIEW_SWAP  the same matrix in the other view: a row view of X gives a
+ *       column view of X (o_row_ptr[R * n_rows + 1]); a column view gives a
+ *       row view (o_row_ptr[n_rows + 1]). Output column ids are X's column ids.
+ * Applying either twice returns X with each row's cells in column order when
+ * they were (generally: grouped by their column's partition, for ViewSwap;
+ * column-sorted, for LocalTranspose). Payload, perm, offset widths,
+ * MGT_FIXED_WIDTH and the errors are as in mgt_transpose; with MGT_VALIDATE a
+ * column outside [0, n_cols), or in column view outside its partition,
+ * also gives MGT_ERANGE. Needs R * n_rows and R * n_cols below 2^31 where
+ * they size a view, else MGT_EUNSUPPORTED.
+ */
+enum { MGT_LOCAL_TRANSPOSE = 0, MGT_VIEW_SWAP = 1 };
+enum { MGT_ROW_VIEW = 0, MGT_COLUMN_VIEW = 1 };
+
+/* Plan for one view operation on matrices described by desc (sizes of X, its
+ * partitions, flags) given in view in_view. Host only. */
+int mgt_view_plan(const mgt_desc* desc, int32_t op, int32_t in_view, mgt_plan_t* out,
+                  size_t* workspace_bytes);
+
+/* Runs the plan's view operation. Inputs as described for the plan's input
+ * view; outputs o_row_ptr (size above), o_col[nnz], o_payload_off[nnz+1],
+ * o_payload[payload_bytes], perm[nnz] (with MGT_EMIT_PERM). */
+int mgt_view_transform(mgt_plan_t plan, const void* row_ptr, const int32_t* col,
+                       const void* payload_off, const uint8_t* payload, void* o_row_ptr,
+                       int32_t* o_col, void* o_payload_off, uint8_t* o_payload, uint32_t* perm,
+                       void* workspace, size_t workspace_bytes, int32_t* d_status,
+                       hipStream_t stream);
+
 /* Capacity of a batch plan. Every submitted batch must fit all limits. */
 typedef struct {
   int32_t max_items;

@@ -22,9 +22,11 @@ of the cells by a key, carrying each cell's payload bytes.
   the block of X's rows in V_r, transposed), and back.
 * ViewSwap (second definition): the same matrix in the orthogonal view.
 
-The paper's claims, which the tests check: both are involutions (up to the
-order of cells inside a row, which comes back column-sorted), and
-Transpose = LocalTranspose . ViewSwap = ViewSwap . LocalTranspose.
+The paper's claims, which the tests check: both are involutions, and
+Transpose = LocalTranspose . ViewSwap = ViewSwap . LocalTranspose. Applied
+twice, LocalTranspose returns every row column-sorted (as T(T(A)) does) and
+ViewSwap returns every row grouped by its columns' partitions, so both give
+the matrix back exactly when its rows are column-sorted.
 """
 from __future__ import annotations
 
@@ -80,9 +82,9 @@ def _stable_by_key(x: ViewCsr, key: np.ndarray, value: np.ndarray, n_out: int):
     poff = np.zeros(order.size + 1, dtype=np.int64)
     np.cumsum(sizes, out=poff[1:])
     starts = x.payload_off[:-1].astype(np.int64)[order]
-    payload = np.empty(int(poff[-1]), dtype=np.uint8)
-    for p in range(order.size):  # plain byte copies, one cell at a time
-        payload[poff[p]:poff[p + 1]] = x.payload[starts[p]:starts[p] + sizes[p]]
+    # output byte b of cell p is input byte starts[p] + (b - poff[p])
+    src = np.repeat(starts - poff[:-1], sizes) + np.arange(int(poff[-1]), dtype=np.int64)
+    payload = x.payload[src] if src.size else np.empty(0, dtype=np.uint8)
     return (row_ptr.astype(dt), value[order].astype(np.int32), poff.astype(dt), payload,
             order.astype(np.uint32))
 

@@ -40,6 +40,7 @@ struct PassArgs {
   uint64_t g8;                // grid size (multiple of 8)
   uint32_t tile_cells;        // multiple of kSub
   int32_t offset_width;
+  int32_t has_val;            // first pass: the items carry vval (view operations)
 };
 
 struct ChildArgs {
@@ -82,6 +83,25 @@ hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_
 hipError_t launch_scan(const uint32_t* in0, uint64_t* out0, const uint32_t* in1, uint64_t* out1,
                        const uint64_t* n_dev, uint64_t n_max, uint64_t* block_sums,
                        hipStream_t s);
+// Per-cell sort key and carried value of a view operation (LocalTranspose or
+// ViewSwap, Section 3) on one item whose bounds are already on the device.
+struct ViewArgs {
+  const ItemDev* items;       // item 0: row_ptr over the virtual rows, status slot
+  const int64_t* bounds;      // device, n_parts + 1 partition bounds of X
+  int32_t n_parts;
+  const int32_t* col;         // the matrix's own column ids
+  uint32_t* keys;             // out: sort key per cell (becomes the item's col)
+  uint32_t* vals;             // out: value per cell (becomes the output column id)
+  uint64_t nnz, n_virtual;    // cells; rows of the input CSR (n_rows, or R * n_rows)
+  int64_t n_rows, n_cols;     // of the matrix X the views represent
+  int32_t op;                 // 0 LocalTranspose, 1 ViewSwap
+  int32_t column_view;        // input is in column view
+  int32_t validate;
+  int32_t offset_width;
+  int32_t* item_status;
+  int32_t* abort_flag;
+};
+hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s);
 hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);

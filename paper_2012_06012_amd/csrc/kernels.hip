@@ -742,14 +742,16 @@ __device__ __forceinline__ void settle(SubLoad& dst, const SubLoad& src) {
 }
 
 // fw >= 0: fixed-width cells; their offsets are k * fw and nothing is loaded
-// for them.
+// for them. val: per-cell carried values (view operations), into d.
 __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, const void* poff,
-                                               uint64_t kfirst, uint32_t n, int lg, int32_t fw) {
+                                               uint64_t kfirst, uint32_t n, int lg, int32_t fw,
+                                               const uint32_t* val) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
     S.a[r] = (uint32_t)gm(col)[kfirst + min(i, n - 1)];
+    if (val) S.d[r] = gm(val)[kfirst + min(i, n - 1)];
   }
   const uint64_t kend = kfirst + min(w * kWaveCells + kWaveCells, n);
   if (fw >= 0) {
@@ -813,7 +815,9 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
 // The records-only pass keeps no byte prefix and no byte cursors, and only a
 // bits-mode fan-out: under 53 KB of LDS and 168 VGPRs, so three workgroups fit
 // on a CU instead of two.
-template <bool kPass0, bool kDefer>
+// kVal (first pass only): every cell carries a value of its own (item vval)
+// in place of its row id, so no rows are expanded.
+template <bool kPass0, bool kDefer, bool kVal>
 __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArgs a) {
   constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
   __shared__ SortLdsT<kFan, !kDefer> L;
@@ -847,7 +851,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   constexpr bool pass0 = kPass0;
-  constexpr int kFields = kPass0 ? kFieldsPass0 : kFieldsRec;
+  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : kFieldsPass0) : kFieldsRec;
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
   const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
   // item fields used in the loop, read once
@@ -869,7 +873,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
   }
   uint32_t r0 = 0;
   RowPf rpf{0, 0}, rpf_next{0, 0};
-  if constexpr (pass0) {
+  if constexpr (pass0 && !kVal) {
     r0 = coop_row_search(i_rp, ow, i_nrows, kbase + c_begin);
     rpf_next = prefetch_row(i_rp, lg, i_nrows, r0);
     rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
@@ -881,7 +885,8 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw);
+    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw,
+                                        kVal ? it->vval : nullptr);
     else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c_begin, n0);
     settle<kFields>(cur, nxt);  // the loop's first iteration then starts from settled registers too
   }
@@ -894,22 +899,28 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
     if constexpr (pass0) {
       const uint64_t kf = kbase + c0;
       sub_base = (uint64_t)cur.base_lo | ((uint64_t)(lg == 3 ? cur.base_hi : 0u) << 32);
-      const uint32_t r_next = expand_rows(i_rp, ow, i_nrows, kf, n, r0, row_word(rpf, lg), L.bpre,
-                                          &s_extra, s_red);
-      rpf_next = prefetch_row(i_rp, lg, i_nrows, r_next);  // next sub-chunk's rows
+      uint32_t r_next = 0;
+      if constexpr (!kVal) {
+        r_next = expand_rows(i_rp, ow, i_nrows, kf, n, r0, row_word(rpf, lg), L.bpre, &s_extra,
+                             s_red);
+        rpf_next = prefetch_row(i_rp, lg, i_nrows, r_next);  // next sub-chunk's rows
+      }
       sizes_from_offsets(cur, sz);
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
         key[r] = cur.a[r];
         src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
-        row[r] = i < n ? r0 + L.bpre[i] : 0u;
+        if constexpr (kVal) row[r] = cur.d[r];
+        else row[r] = i < n ? r0 + L.bpre[i] : 0u;
         idx[r] = (uint32_t)(kf + i);
       }
-      first_row = r0;
-      last_row = r0 + L.bpre[n - 1];
-      r0 = r_next;
-      __syncthreads();  // rows consumed before sort_sub reuses the buffer
+      if constexpr (!kVal) {
+        first_row = r0;
+        last_row = r0 + L.bpre[n - 1];
+        r0 = r_next;
+        __syncthreads();  // rows consumed before sort_sub reuses the buffer
+      }
     } else {
       sub_base = src_sub;
 #pragma unroll
@@ -929,7 +940,8 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
     // issuing these would wait for these too) and fly during the sort.
     if (c1 < c_end) {
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw);
+      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
+                                          kVal ? it->vval : nullptr);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
     }
     sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
@@ -1025,7 +1037,65 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
     }
     __syncthreads();
     settle<kFields>(cur, nxt);
-    if constexpr (pass0) rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
+    if constexpr (pass0 && !kVal) rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
+  }
+}
+
+// ----------------------------------------------------------------------------- view keys
+
+// Sort key and carried value of every cell for LocalTranspose and ViewSwap
+// (Section 3). Both are stable sorts of the cells by a key, so they run
+// through the same passes as the transpose, with the key in place of the
+// column and the value in place of the row id. X is the matrix the views
+// represent (n_rows x n_cols, partitions V_p = [b_p, b_p+1)). A row-view input
+// is X's CSR; a column-view input stores partition s (X restricted to the
+// columns V_s) as a CSR over all rows, partition after partition (virtual row
+// v = s * n_rows + i).
+//   LocalTranspose, row view:    key = owner(i) * n_cols + j, value i
+//   LocalTranspose, column view: key = j,                     value i
+//   ViewSwap, row view:          key = owner(j) * n_rows + i, value j
+//   ViewSwap, column view:       key = i,                     value j
+// With validation, a column outside [0, n_cols) or, in column view, outside
+// its partition's range sets MGT_ERANGE.
+__global__ __launch_bounds__(kBlock) void k_view_keys(ViewArgs a) {
+  __shared__ uint32_t incl[kSub];
+  __shared__ int32_t s_lb[kMaxParts + 1];
+  __shared__ uint32_t s_extra;
+  __shared__ uint32_t s_red[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  const ItemDev& it = a.items[0];
+  const uint32_t R = (uint32_t)a.n_parts;
+  for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(a.bounds)[i];
+  __syncthreads();
+  const uint64_t k0 = (uint64_t)blockIdx.x * kSub;
+  if (k0 >= a.nnz) return;
+  const uint32_t n = (uint32_t)min((uint64_t)kSub, a.nnz - k0);
+  const int ow = a.offset_width, lg = ow == 8 ? 3 : 2;
+  const uint32_t r0 = coop_row_search(it.row_ptr, ow, a.n_virtual, k0);
+  const RowPf pf = prefetch_row(it.row_ptr, lg, a.n_virtual, r0);
+  expand_rows(it.row_ptr, ow, a.n_virtual, k0, n, r0, row_word(pf, lg), incl, &s_extra, s_red);
+  bool bad = false;
+  for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
+    const uint64_t k = k0 + i;
+    const uint64_t v = (uint64_t)r0 + incl[i];  // virtual row of cell k
+    const int64_t j = gm(a.col)[k];
+    uint64_t key, val;
+    if (!a.column_view) {
+      key = a.op == 0 ? (uint64_t)owner_of(s_lb, R, (int64_t)v) * (uint64_t)a.n_cols + (uint64_t)j
+                      : (uint64_t)owner_of(s_lb, R, j) * (uint64_t)a.n_rows + v;
+      val = a.op == 0 ? v : (uint64_t)j;
+      if (a.validate && (j < 0 || j >= a.n_cols)) bad = true;
+    } else {
+      const uint64_t s = v / (uint64_t)a.n_rows, i_row = v - s * (uint64_t)a.n_rows;
+      key = a.op == 0 ? (uint64_t)j : i_row;
+      val = a.op == 0 ? i_row : (uint64_t)j;
+      if (a.validate && (j < 0 || j >= a.n_cols || owner_of(s_lb, R, j) != s)) bad = true;
+    }
+    gm(a.keys)[k] = (uint32_t)key;
+    gm(a.vals)[k] = (uint32_t)val;
+  }
+  if (__syncthreads_or(bad)) {
+    if (threadIdx.x == 0) raise_status(a.item_status, a.abort_flag, it.status_index, MGT_ERANGE);
   }
 }
 
@@ -1370,10 +1440,21 @@ hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s) {
 
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
   if (a.g8) {
-    if (a.pass == 0) hipLaunchKernelGGL((k_pass_scatter<true, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
-    else if (a.so_out) hipLaunchKernelGGL((k_pass_scatter<false, true>), grid1(a.g8), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_pass_scatter<false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    if (a.pass == 0 && a.has_val)
+      hipLaunchKernelGGL((k_pass_scatter<true, false, true>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    else if (a.pass == 0)
+      hipLaunchKernelGGL((k_pass_scatter<true, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    else if (a.so_out)
+      hipLaunchKernelGGL((k_pass_scatter<false, true, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_pass_scatter<false, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s) {
+  const uint64_t nb = (a.nnz + kSub - 1) / kSub;
+  if (nb) hipLaunchKernelGGL(k_view_keys, grid1(nb), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -57,6 +57,8 @@ struct ItemDev {
   int64_t* sdispls;
   int64_t* rdispls;
   const int64_t* bounds;      // device copy, n_parts + 1 entries
+  const uint32_t* vval;       // per input cell: the value the output carries instead of the
+                              // row id (view operations), or null
   int64_t n_rows, n_cols, nnz, payload_bytes;
   uint64_t cell_base;         // first cell of the item in the level buffers
   uint64_t byte_base;         // first payload byte of the item in the level buffers

@@ -146,11 +146,16 @@ struct Layout {
       o_hstart[kMaxLevels];
   uint64_t o_hcnt, o_hbyt, o_ocnt, o_obyt, o_ttot, o_tsrc, o_scan;
   uint64_t o_ks[2], o_rk[2], o_pay[2], o_so = 0;
+  // view operations: partition bounds of the matrix, per-cell keys and values
+  uint64_t n_vbounds = 0, o_vbounds = 0, o_vkeys = 0, o_vvals = 0;
   uint64_t bytes = 0;
 };
 
-Layout make_layout(std::vector<HostItem>& items) {
+// n_vbounds > 0: a view operation on the single item, whose matrix has
+// n_vbounds - 1 partitions.
+Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   Layout y;
+  y.n_vbounds = n_vbounds;
   y.n_items = (uint32_t)items.size();
   int L = 1;
   for (auto& it : items) L = std::max(L, it.s.n_levels);
@@ -211,6 +216,7 @@ Layout make_layout(std::vector<HostItem>& items) {
   y.o_status = take(4ull * y.n_items);
   y.o_abort = take(64);
   y.o_bounds = take(8ull * y.total_bounds);
+  if (n_vbounds) y.o_vbounds = take(8ull * n_vbounds);  // uploaded with the bounds
   for (int l = 0; l <= L; ++l) y.o_segs[l] = take(sizeof(Seg) * y.nseg[l]);
   for (int l = 0; l < L; ++l) {
     y.o_tcnt[l] = take(4ull * y.nseg[l]);
@@ -242,6 +248,10 @@ Layout make_layout(std::vector<HostItem>& items) {
     y.o_pay[b] = b < npay ? take(y.total_bytes + 16) : y.o_pay[0];
   }
   if (L >= 2) y.o_so = take(8ull * y.total_nnz);
+  if (n_vbounds) {
+    y.o_vkeys = take(4ull * y.total_nnz);
+    y.o_vvals = take(4ull * y.total_nnz);
+  }
   y.bytes = o + 256;
   return y;
 }
@@ -292,6 +302,11 @@ struct mgt_plan_s {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   Timing timing;
+  // view-operation plans (mgt_view_plan): the operation, the input view, and
+  // the descriptor the passes see (virtual rows, sort keys as columns)
+  int32_t view_op = -1, column_view = 0;
+  mgt_desc view_desc{};
+  size_t ws_view = 0;
 };
 
 namespace {
@@ -333,13 +348,22 @@ void time_mark(mgt_plan_s* p, hipStream_t s, const char* name) {
   } while (0)
 
 // Runs the whole pipeline for `items` (already scheduled and laid out).
+// A view operation's parameters (see k_view_keys).
+struct ViewCall {
+  const int32_t* col;       // the matrix's own column ids
+  const int64_t* bounds;    // host, n_vbounds entries
+  int64_t n_rows, n_cols;   // of the matrix X
+  int32_t op, column_view;
+};
+
 int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, int32_t* d_status,
-        hipStream_t s) {
+        hipStream_t s, const ViewCall* vc = nullptr) {
   uint8_t* W = (uint8_t*)ws;
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
   // 1. upload items + bounds through the pinned staging buffer
-  const size_t up_bytes = y.o_bounds + 8ull * y.total_bounds;
+  const size_t up_bytes = y.n_vbounds ? y.o_vbounds + 8ull * y.n_vbounds
+                                      : y.o_bounds + 8ull * y.total_bounds;
   int st = ensure_staging(p, up_bytes);
   if (st != MGT_OK) return st;
   uint8_t* H = (uint8_t*)p->staging;
@@ -367,6 +391,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     bo += (uint64_t)it.d.n_parts + 1;
     std::memcpy(H + y.o_items + sizeof(ItemDev) * i, &d, sizeof(ItemDev));
   }
+  if (vc) std::memcpy(H + y.o_vbounds, vc->bounds, 8ull * y.n_vbounds);
   time_mark(p, s, "start");
   MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
   MGT_HIP(hipEventRecord(p->upload_done, s));
@@ -389,6 +414,26 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   uint64_t* scan = (uint64_t*)(W + y.o_scan);
 
   MGT_HIP(launch_init(d_items, n, segs(0), tcnt(0), hsz(0), d_item_status, d_abort, kTileCells, s));
+  if (vc) {
+    ViewArgs v{};
+    v.items = d_items;
+    v.bounds = (const int64_t*)(W + y.o_vbounds);
+    v.n_parts = (int32_t)(y.n_vbounds - 1);
+    v.col = vc->col;
+    v.keys = (uint32_t*)(W + y.o_vkeys);
+    v.vals = (uint32_t*)(W + y.o_vvals);
+    v.nnz = (uint64_t)items[0].d.nnz;
+    v.n_virtual = (uint64_t)items[0].d.n_rows;
+    v.n_rows = vc->n_rows;
+    v.n_cols = vc->n_cols;
+    v.op = vc->op;
+    v.column_view = vc->column_view;
+    v.validate = (p->flags & MGT_VALIDATE) ? 1 : 0;
+    v.offset_width = ow;
+    v.item_status = d_item_status;
+    v.abort_flag = d_abort;
+    MGT_HIP(launch_view_keys(v, s));
+  }
   if (p->flags & MGT_VALIDATE) {
     uint64_t max_len = 0;
     for (auto& it : items) max_len = std::max<uint64_t>(max_len, (uint64_t)std::max(it.d.n_rows, it.d.nnz));
@@ -426,6 +471,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.g8 = align_up(y.tiles_max[l], 8);
     a.tile_cells = kTileCells;
     a.offset_width = ow;
+    a.has_val = (vc && l == 0) ? 1 : 0;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];
@@ -507,7 +553,7 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
                 void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xc, int64_t* xb,
                 int64_t* pco, int64_t* pbo, int64_t* sd, int64_t* rd, void* ws, size_t ws_bytes,
                 int32_t* d_status, hipStream_t s) {
-  if (!p || p->batch) return MGT_EINVAL;
+  if (!p || p->batch || p->view_op >= 0) return MGT_EINVAL;
   const mgt_desc& d = p->desc;
   int st = check_io(d, p->flags, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
                     t_payload, perm);
@@ -646,6 +692,78 @@ int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_
   return single_call(plan, true, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
                      t_payload, perm, xfer_cells, xfer_bytes, part_cell_off, part_byte_off, sdispls,
                      rdispls, workspace, workspace_bytes, d_status, stream);
+}
+
+int mgt_view_plan(const mgt_desc* desc, int32_t op, int32_t in_view, mgt_plan_t* out,
+                  size_t* workspace_bytes) {
+  if (!out) return MGT_EINVAL;
+  if ((op != MGT_LOCAL_TRANSPOSE && op != MGT_VIEW_SWAP) ||
+      (in_view != MGT_ROW_VIEW && in_view != MGT_COLUMN_VIEW))
+    return MGT_EINVAL;
+  int st = check_desc(desc, false);
+  if (st != MGT_OK) return st;
+  if ((desc->flags & ~(uint32_t)(MGT_VALIDATE | MGT_EMIT_PERM | MGT_DEBUG_TIMING | MGT_FIXED_WIDTH)) != 0)
+    return MGT_EINVAL;
+  const int64_t R = desc->n_parts;
+  if (R > 1 && desc->n_rows != desc->n_cols) return MGT_EINVAL;
+  if (desc->nnz > 0 && (desc->n_rows == 0 || desc->n_cols == 0)) return MGT_EINVAL;
+  const int64_t n_virtual = in_view == MGT_COLUMN_VIEW ? R * desc->n_rows : desc->n_rows;
+  int64_t n_key;
+  if (op == MGT_LOCAL_TRANSPOSE) n_key = in_view == MGT_ROW_VIEW ? R * desc->n_cols : desc->n_cols;
+  else n_key = in_view == MGT_ROW_VIEW ? R * desc->n_rows : desc->n_rows;
+  if (n_virtual >= (1ll << 31) || n_key >= (1ll << 31)) return MGT_EUNSUPPORTED;
+  mgt_plan_s* p = new (std::nothrow) mgt_plan_s();
+  if (!p) return MGT_ENOMEM;
+  p->desc = *desc;
+  p->flags = desc->flags;
+  if (desc->part_bounds) p->bounds.assign(desc->part_bounds, desc->part_bounds + R + 1);
+  else p->bounds = {0, desc->n_rows};
+  p->desc.part_bounds = p->bounds.data();
+  p->view_op = op;
+  p->column_view = in_view == MGT_COLUMN_VIEW;
+  mgt_desc v = *desc;
+  v.n_rows = n_virtual;
+  v.n_cols = n_key;
+  v.n_parts = 1;
+  v.part_bounds = nullptr;
+  p->view_desc = v;
+  std::vector<HostItem> items(1);
+  items[0].d = v;
+  items[0].bounds = nullptr;
+  items[0].s = make_sched(v.n_cols, v.nnz, 1, nullptr, false);
+  std::memset(&items[0].dev, 0, sizeof(ItemDev));
+  p->ws_view = make_layout(items, (uint64_t)R + 1).bytes;
+  *out = p;
+  if (workspace_bytes) *workspace_bytes = p->ws_view;
+  return MGT_OK;
+}
+
+int mgt_view_transform(mgt_plan_t p, const void* row_ptr, const int32_t* col,
+                       const void* payload_off, const uint8_t* payload, void* o_row_ptr,
+                       int32_t* o_col, void* o_payload_off, uint8_t* o_payload, uint32_t* perm,
+                       void* workspace, size_t workspace_bytes, int32_t* d_status,
+                       hipStream_t stream) {
+  if (!p || p->batch || p->view_op < 0) return MGT_EINVAL;
+  const mgt_desc& v = p->view_desc;
+  int st = check_io(v, p->flags, row_ptr, col, payload_off, payload, o_row_ptr, o_col, o_payload_off,
+                    o_payload, perm);
+  if (st != MGT_OK) return st;
+  if (!workspace || ((uintptr_t)workspace & 255u)) return MGT_EINVAL;
+  std::vector<HostItem> items(1);
+  HostItem& it = items[0];
+  it.d = v;
+  it.bounds = nullptr;
+  it.s = make_sched(v.n_cols, v.nnz, 1, nullptr, false);
+  fill_outputs(it.dev, row_ptr, col, payload_off, payload, o_row_ptr, o_col, o_payload_off,
+               o_payload, perm);
+  Layout y = make_layout(items, p->bounds.size());
+  if (workspace_bytes < y.bytes) return MGT_ENOMEM;
+  uint8_t* W = (uint8_t*)workspace;
+  it.dev.col = (const int32_t*)(W + y.o_vkeys);  // the passes sort by the keys ...
+  it.dev.vval = (const uint32_t*)(W + y.o_vvals);  // ... and carry the values
+  ViewCall vc{col, p->bounds.data(), p->desc.n_rows, p->desc.n_cols, p->view_op, p->column_view};
+  p->timing.used = 0;
+  return run(p, items, y, workspace, d_status, stream, &vc);
 }
 
 int mgt_batch_plan(const mgt_batch_limits* lim, mgt_plan_t* out, size_t* workspace_bytes) {

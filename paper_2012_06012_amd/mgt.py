@@ -24,6 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libmgt.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED, ECANCELED = 0, -1, -2, -3, -4, -5, -6
 VALIDATE, EMIT_PERM, DEBUG_TIMING, FIXED_WIDTH = 1, 2, 4, 8
+LOCAL_TRANSPOSE, VIEW_SWAP = 0, 1
+ROW_VIEW, COLUMN_VIEW = 0, 1
 _NAMES = {0: "MGT_OK", -1: "MGT_EINVAL", -2: "MGT_ERANGE", -3: "MGT_ENOMEM", -4: "MGT_EHIP",
           -5: "MGT_EUNSUPPORTED", -6: "MGT_ECANCELED"}
 
@@ -71,14 +73,18 @@ _lib.mgt_batch_workspace.argtypes = [_vp, ctypes.POINTER(Item), _i32, ctypes.POI
 _lib.mgt_batch_submit.argtypes = [_vp, ctypes.POINTER(Item), _i32, _vp, _sz, _vp, _vp, _vp]
 _lib.mgt_plan_stage_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_char_p), _i32, ctypes.POINTER(_i32)]
+_lib.mgt_view_plan.argtypes = [ctypes.POINTER(Desc), _i32, _i32, ctypes.POINTER(_vp),
+                               ctypes.POINTER(_sz)]
+_lib.mgt_view_transform.argtypes = [_vp] * 10 + [_vp, _sz, _vp, _vp]
 _lib.mgt_version.restype = ctypes.c_char_p
 for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
-           "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times"):
+           "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
+           "mgt_view_plan", "mgt_view_transform"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
             "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
-            "mgt_version")
+            "mgt_version", "mgt_view_plan", "mgt_view_transform")
 
 
 def version() -> str:
@@ -178,6 +184,29 @@ def mgt_transpose_partitioned(plan: Plan, row_ptr, col, payload_off, payload, t_
         _ptr(xfer_bytes), _ptr(part_cell_off), _ptr(part_byte_off), _ptr(sdispls), _ptr(rdispls),
         _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(d_status),
         _stream(stream)), "mgt_transpose_partitioned")
+
+
+def mgt_view_plan(n_rows: int, n_cols: int, nnz: int, payload_bytes: int, offset_width: int,
+                  part_bounds: Optional[Sequence[int]], op: int, in_view: int,
+                  flags: int = 0) -> Plan:
+    b = None if part_bounds is None else np.ascontiguousarray(part_bounds, dtype=np.int64)
+    d = Desc(n_rows, n_cols, nnz, payload_bytes, offset_width,
+             1 if b is None else len(b) - 1, None if b is None else b.ctypes.data, flags)
+    h = _vp()
+    ws = _sz()
+    _check(_lib.mgt_view_plan(ctypes.byref(d), op, in_view, ctypes.byref(h), ctypes.byref(ws)),
+           "mgt_view_plan")
+    return Plan(h.value, ws.value, d, False, b)
+
+
+def mgt_view_transform(plan: Plan, row_ptr, col, payload_off, payload, o_row_ptr, o_col,
+                       o_payload_off, o_payload, perm, workspace, d_status=None,
+                       stream=None) -> None:
+    _check(_lib.mgt_view_transform(plan.handle, _ptr(row_ptr), _ptr(col), _ptr(payload_off),
+                                   _ptr(payload), _ptr(o_row_ptr), _ptr(o_col),
+                                   _ptr(o_payload_off), _ptr(o_payload), _ptr(perm),
+                                   _ptr(workspace), workspace.numel(), _ptr(d_status),
+                                   _stream(stream)), "mgt_view_transform")
 
 
 def make_items(entries) -> ctypes.Array:
@@ -344,3 +373,39 @@ def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm
     mgt_batch_submit(plan, items, workspace, status, stream, done_event)
     del keep
     return outs, status, plan, workspace
+
+
+def view_out_rows(n_rows: int, n_cols: int, n_parts: int, op: int, in_view: int) -> int:
+    """Rows of a view operation's output CSR (see mgt_view_plan)."""
+    if op == LOCAL_TRANSPOSE:
+        return n_parts * n_cols if in_view == ROW_VIEW else n_cols
+    return n_parts * n_rows if in_view == ROW_VIEW else n_rows
+
+
+def view_transform(row_ptr, col, payload_off, payload, n_rows: int, n_cols: int, bounds,
+                   offset_width: int, op: int, in_view: int, perm: bool = False,
+                   validate: bool = False, fixed_width: bool = False, plan: Optional[Plan] = None,
+                   workspace=None, stream=None):
+    """Allocates outputs and runs mgt_view_transform (LocalTranspose or
+    ViewSwap of the matrix X, n_rows x n_cols, with the given partition bounds,
+    held in view in_view). Returns (outputs dict, status tensor)."""
+    flags = ((EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+             | (FIXED_WIDTH if fixed_width else 0))
+    nnz, nbytes = int(col.numel()), int(payload.numel())
+    b = np.ascontiguousarray(bounds, dtype=np.int64)
+    if plan is None:
+        plan = mgt_view_plan(n_rows, n_cols, nnz, nbytes, offset_width, b, op, in_view, flags)
+    dev = col.device
+    if workspace is None:
+        workspace = workspace_for(plan, dev)
+    odt = torch.int32 if offset_width == 4 else torch.int64
+    n_out = view_out_rows(n_rows, n_cols, len(b) - 1, op, in_view)
+    out = dict(row_ptr=torch.empty(n_out + 1, dtype=odt, device=dev),
+               col=torch.empty(nnz, dtype=torch.int32, device=dev),
+               payload_off=(None if fixed_width else torch.empty(nnz + 1, dtype=odt, device=dev)),
+               payload=torch.empty(nbytes, dtype=torch.uint8, device=dev),
+               perm=torch.empty(nnz, dtype=torch.int32, device=dev) if perm else None)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    mgt_view_transform(plan, row_ptr, col, payload_off, payload, out["row_ptr"], out["col"],
+                       out["payload_off"], out["payload"], out["perm"], workspace, status, stream)
+    return out, status

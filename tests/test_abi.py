@@ -135,6 +135,33 @@ def test_fixed_width_descriptor_and_offset_pointers():
     assert rc == -3
 
 
+def test_view_plans():
+    mgt = _lib()
+    b = [0, 30, 100]
+    for op in (mgt.LOCAL_TRANSPOSE, mgt.VIEW_SWAP):
+        for view in (mgt.ROW_VIEW, mgt.COLUMN_VIEW):
+            assert mgt.mgt_view_plan(100, 100, 500, 2000, 8, b, op, view).workspace_bytes > 0
+    for args, code in [((100, 90, 500, 2000, 8, b, 0, 0), -1),     # partitioned, not square
+                       ((100, 100, 500, 2000, 8, b, 2, 0), -1),    # unknown operation
+                       ((100, 100, 500, 2000, 8, b, 0, 2), -1),    # unknown view
+                       ((1 << 21, 1 << 21, 10, 0, 8,               # R * n_cols >= 2^31
+                         np.linspace(0, 1 << 21, 1025).astype(np.int64), 0, 0), -5)]:
+        with pytest.raises(mgt.MgtError) as e:
+            mgt.mgt_view_plan(*args)
+        assert e.value.code == code
+    # with one partition the matrix may be rectangular
+    assert mgt.mgt_view_plan(50, 80, 100, 0, 4, None, mgt.VIEW_SWAP, mgt.ROW_VIEW).workspace_bytes
+    # a view plan is not a transpose plan
+    p = mgt.mgt_view_plan(10, 10, 5, 0, 8, None, mgt.LOCAL_TRANSPOSE, mgt.ROW_VIEW)
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    lib.mgt_transpose.argtypes = [ctypes.c_void_p] * 10 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                          ctypes.c_void_p, ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)
+    rc = lib.mgt_transpose(p.handle, fake, fake, fake, None, fake, fake, fake, None, None, fake,
+                           1 << 30, None, None)
+    assert rc == -1
+
+
 def test_partitioned_rejects_missing_outputs():
     mgt = _lib()
     p = mgt.mgt_plan(10, 10, 5, 0, 8, [0, 5, 10])

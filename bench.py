@@ -44,10 +44,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
     if stage == "scatter" and pass_idx == 0:
         return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + rec + P
     if stage == "scatter" and deferred and pass_idx == n_passes - 1:
-        return rec + rec + 8 * nnz
+        return rec + 8 * nnz + 16 * nnz  # (column, size) and (row, index, payload offset) out
     if stage == "scatter":
         return 2 * (rec + P)
-    if stage == "finish":
+    if stage == "finish":  # after a records-only pass its records are 8 + 16 bytes
         return (rec + (8 * nnz if deferred else 0) + P + nnz * (4 + (4 if perm else 0))
                 + (nnz + 1) * o + (a.n_cols + 1) * o + P)
     if stage == "hist" and pass_idx == 0:
@@ -128,7 +128,7 @@ def bench_batch(args):
     from paper_2012_06012_amd import mgt
     dev = torch.device("cuda:0")
     t0 = time.time()
-    host = [gen.batch_item(args.seed, i, 1e3, 1e5) for i in range(args.items)]
+    host = [gen.batch_item(args.seed, i, 1e3, args.batch_n_hi) for i in range(args.items)]
     mats = [_device(a, dev) for a in host]
     cells = sum(a.nnz for a in host)
     log(f"[batch] {len(host)} matrices, {cells} cells, generated in {time.time() - t0:.1f}s")
@@ -162,8 +162,9 @@ def bench_batch(args):
            "cells_per_s_batched": cells / (ms_batch * 1e-3),
            "cells_per_s_plain": cells / (ms_plain * 1e-3), "speedup": ms_plain / ms_batch,
            "bit_exact_batched_vs_plain": bool(same),
-           "config": {"workload": "batch of matrices, n log-uniform 1e3-1e5, mean degree U{8..64}, "
-                                  "payload U{0..16} bytes per matrix", "seed": args.seed}}
+           "config": {"workload": f"batch of matrices, n log-uniform 1e3-{args.batch_n_hi:.0e}, "
+                                  "mean degree U{8..64}, payload U{0..16} bytes per matrix",
+                      "seed": args.seed}}
     print(json.dumps(res), flush=True)
 
 
@@ -201,14 +202,20 @@ def bench_serve(args):
     mu = 64 / st.last_done
     log(f"[serve] plain capacity {mu:.1f} req/s")
     out = {}
-    for frac in (0.7, 1.2):
+    bex = serve.GpuExecutor(n_slots=2, max_items=64)
+    pex = serve.PlainExecutor()
+    warm = 64  # warm-up requests per rate: device allocations are made and cached there
+    for frac in (0.5, 0.7, 0.9, 1.2):
         rate = frac * mu
-        sb = Server(serve.GpuExecutor(n_slots=2, max_items=64), budget, max_batch=32, n_slots=2).run(make(rate))
-        sp = Server(serve.PlainExecutor(), budget, max_batch=1, n_slots=1).run(make(rate))
+        Server(bex, budget, max_batch=32, n_slots=2).run(make(rate)[:warm])
+        sb = Server(bex, budget, max_batch=32, n_slots=2).run(make(rate))
+        Server(pex, budget, max_batch=1, n_slots=1).run(make(rate)[:warm])
+        sp = Server(pex, budget, max_batch=1, n_slots=1).run(make(rate))
         out[f"{frac}mu"] = {"batched": sb.summary(), "plain": sp.summary()}
         log(f"[serve] rate {rate:.1f}/s: batched {sb.summary()} plain {sp.summary()}")
     res = {"metric": "served p50/p99 latency and sustained cells/s, batched vs plain",
-           "mode": "serve", "requests": n_req, "plain_capacity_req_s": mu, "results": out,
+           "mode": "serve", "requests": n_req, "warmup_requests": warm,
+           "plain_capacity_req_s": mu, "results": out,
            "config": {"workload": "requests of log-uniform 1e4-1e7 cells, widths U{0..32}, "
                                   "R U{1..64}, Poisson arrivals", "budget_bytes": budget}}
     print(json.dumps(res), flush=True)
@@ -374,6 +381,8 @@ def main():
                          "vs per-matrix launches; serve: the continuous-batching request loop vs "
                          "per-request plain launches")
     ap.add_argument("--items", type=int, default=512, help="batch / serve: matrices or requests")
+    ap.add_argument("--batch-n-hi", type=float, default=1e6,
+                    help="batch: largest matrix size of the log-uniform range")
     ap.add_argument("--fixed-width", action="store_true",
                     help="hetero: run the fixed-width mode (no payload offsets on the device)")
     args = ap.parse_args()

@@ -26,9 +26,10 @@ struct PassArgs {
   const uint8_t* pay_in;      // payload bytes, pass >= 2
   uint2* ks_out;
   uint2* rk_out;
-  uint8_t* pay_out;           // unused when so_out is set
-  uint64_t* so_out;           // last pass of two or more: per-cell byte offset of the payload
-                              // in pay_in; no payload is moved
+  uint8_t* pay_out;           // unused when rso_out is set
+  uint32_t* rso_out;          // last pass of two or more: per cell (row, cell index, byte
+                              // offset of the payload in pay_in as two words) in place of
+                              // rk_out; no payload is moved
   uint32_t* hcnt;             // [entry] cells of (segment, digit, tile)
   uint32_t* hbyt;             // [entry] payload bytes of (segment, digit, tile)
   uint32_t* ttot;             // [tile] payload bytes of the tile
@@ -65,8 +66,9 @@ struct FinishArgs {
   uint32_t nbuckets;
   const uint2* ks_in;
   const uint2* rk_in;
-  const uint8_t* pay_in;      // payload level buffer (the one before the last pass if so_in)
-  const uint64_t* so_in;      // per-cell payload offsets in pay_in from the last pass, or null
+  const uint8_t* pay_in;      // payload level buffer (the one before the last pass if rso_in)
+  const uint32_t* rso_in;     // (row, cell index, payload offset in pay_in) records of the
+                              // last pass, read in place of rk_in, or null
   const int32_t* abort_flag;
   int32_t offset_width;
   uint64_t g8;                // grid size (multiple of 8)

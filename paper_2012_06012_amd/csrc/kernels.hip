@@ -621,6 +621,7 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
 constexpr int kPay = 4;  // cells per lane whose payload words are held at once
 
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte aligned record
 typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
 struct PayRegs {
   u32x4a v[kPay][2];
@@ -778,18 +779,19 @@ __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, c
 }
 
 __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
-                                             const uint64_t* so, uint64_t pos0, uint32_t n) {
+                                             const uint32_t* rso, uint64_t pos0, uint32_t n) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
     const uint2 x = ks[pos0 + i];
-    const uint2 y = rk[pos0 + i];
-    S.a[r] = x.x; S.b[r] = x.y; S.c[r] = y.x; S.d[r] = y.y;
-    if (so) {
-      const uint64_t v = gm(so)[pos0 + i];
-      S.e[r] = (uint32_t)v;
-      S.f[r] = (uint32_t)(v >> 32);
+    S.a[r] = x.x; S.b[r] = x.y;
+    if (rso) {  // (row, cell index, payload offset) records of a records-only pass
+      const v4u y = gm((const v4u*)rso)[pos0 + i];
+      S.c[r] = y.x; S.d[r] = y.y; S.e[r] = y.z; S.f[r] = y.w;
+    } else {
+      const uint2 y = rk[pos0 + i];
+      S.c[r] = y.x; S.d[r] = y.y;
     }
   }
 }
@@ -963,8 +965,13 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
           const uint32_t d = L.dig[i];
           const uint64_t cd = seg_out + s_rc[d] + (i - L.wc[d * kNW]);
           a.ks_out[cd] = make_uint2(L.key[i], L.sz[i]);
-          a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
-          gm(a.so_out)[cd] = sub_base + L.src[i];
+          const uint64_t so = sub_base + L.src[i];
+          v4u rec;
+          rec.x = L.row[i];
+          rec.y = L.idx[i];
+          rec.z = (uint32_t)so;
+          rec.w = (uint32_t)(so >> 32);
+          gm((v4u*)a.rso_out)[cd] = rec;
         }
       }
     }
@@ -1107,7 +1114,7 @@ __global__ __launch_bounds__(kBlock) void k_view_keys(ViewArgs a) {
 template <bool kGather>
 __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   constexpr int kFields = kGather ? kFieldsRecSo : kFieldsRec;
-  const uint64_t* const so = kGather ? a.so_in : nullptr;
+  const uint32_t* const so = kGather ? a.rso_in : nullptr;
   __shared__ SortLds L;
   __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
   __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
@@ -1444,7 +1451,7 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((k_pass_scatter<true, false, true>), grid1(a.g8), dim3(kBlock), 0, s, a);
     else if (a.pass == 0)
       hipLaunchKernelGGL((k_pass_scatter<true, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
-    else if (a.so_out)
+    else if (a.rso_out)
       hipLaunchKernelGGL((k_pass_scatter<false, true, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
     else
       hipLaunchKernelGGL((k_pass_scatter<false, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
@@ -1465,7 +1472,7 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
   if (a.nbuckets) {
-    if (a.so_in) hipLaunchKernelGGL(k_finish<true>, grid1(a.g8), dim3(kBlock), 0, s, a);
+    if (a.rso_in) hipLaunchKernelGGL(k_finish<true>, grid1(a.g8), dim3(kBlock), 0, s, a);
     else hipLaunchKernelGGL(k_finish<false>, grid1(a.g8), dim3(kBlock), 0, s, a);
   }
   return hipGetLastError();

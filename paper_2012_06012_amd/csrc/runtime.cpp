@@ -145,7 +145,7 @@ struct Layout {
   uint64_t o_segs[kMaxLevels + 1], o_tcnt[kMaxLevels], o_hsz[kMaxLevels], o_tstart[kMaxLevels],
       o_hstart[kMaxLevels];
   uint64_t o_hcnt, o_hbyt, o_ocnt, o_obyt, o_ttot, o_tsrc, o_scan;
-  uint64_t o_ks[2], o_rk[2], o_pay[2], o_so = 0;
+  uint64_t o_ks[2], o_rk[2], o_pay[2], o_rso = 0;
   // view operations: partition bounds of the matrix, per-cell keys and values
   uint64_t n_vbounds = 0, o_vbounds = 0, o_vkeys = 0, o_vvals = 0;
   uint64_t bytes = 0;
@@ -231,23 +231,19 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   y.o_ttot = take(4ull * y.tiles_all_max);
   y.o_tsrc = take(8ull * (y.tiles_all_max + 1));
   y.o_scan = take(scan_scratch_bytes(y.scan_max));
-  // Records ping-pong between two level buffers. Payload bytes are written
-  // by every pass but the last when there are two or more passes (the last
-  // one records an 8-byte payload offset per cell instead), so a second
-  // payload buffer is needed only from three passes on.
-  const int nbuf = L >= 2 ? 2 : 1;
-  const int npay = L >= 3 ? 2 : 1;
+  // Records ping-pong between two level buffers. With two or more passes the
+  // last one writes (row, cell index, payload offset) records of 16 bytes in
+  // place of the 8-byte (row, cell index) ones, and no payload: a second
+  // payload buffer, and a second (row, index) buffer, are needed only from
+  // three passes on.
+  const int nks = L >= 2 ? 2 : 1;
+  const int nrk = L >= 3 ? 2 : 1;
   for (int b = 0; b < 2; ++b) {
-    if (b < nbuf) {
-      y.o_ks[b] = take(8ull * y.total_nnz);
-      y.o_rk[b] = take(8ull * y.total_nnz);
-    } else {
-      y.o_ks[b] = y.o_ks[0];
-      y.o_rk[b] = y.o_rk[0];
-    }
-    y.o_pay[b] = b < npay ? take(y.total_bytes + 16) : y.o_pay[0];
+    y.o_ks[b] = b < nks ? take(8ull * y.total_nnz) : y.o_ks[0];
+    y.o_rk[b] = b < nrk ? take(8ull * y.total_nnz) : y.o_rk[0];
+    y.o_pay[b] = b < nrk ? take(y.total_bytes + 16) : y.o_pay[0];
   }
-  if (L >= 2) y.o_so = take(8ull * y.total_nnz);
+  if (L >= 2) y.o_rso = take(16ull * y.total_nnz);
   if (n_vbounds) {
     y.o_vkeys = take(4ull * y.total_nnz);
     y.o_vvals = take(4ull * y.total_nnz);
@@ -458,8 +454,11 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.ks_out = (uint2*)(W + y.o_ks[bo2]);
     a.rk_out = (uint2*)(W + y.o_rk[bo2]);
     a.pay_out = (uint8_t*)(W + y.o_pay[bo2]);
-    a.so_out = (L >= 2 && l == L - 1) ? (uint64_t*)(W + y.o_so) : nullptr;
-    if (a.so_out) a.pay_out = nullptr;
+    a.rso_out = (L >= 2 && l == L - 1) ? (uint32_t*)(W + y.o_rso) : nullptr;
+    if (a.rso_out) {
+      a.pay_out = nullptr;
+      a.rk_out = nullptr;
+    }
     a.hcnt = hcnt;
     a.hbyt = hbyt;
     a.ttot = ttot;
@@ -506,7 +505,8 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.ks_in = (const uint2*)(W + y.o_ks[bl]);
   f.rk_in = (const uint2*)(W + y.o_rk[bl]);
   f.pay_in = (const uint8_t*)(W + y.o_pay[L >= 2 ? (L - 2) & 1 : bl]);
-  f.so_in = L >= 2 ? (const uint64_t*)(W + y.o_so) : nullptr;
+  f.rso_in = L >= 2 ? (const uint32_t*)(W + y.o_rso) : nullptr;
+  if (f.rso_in) f.rk_in = nullptr;
   f.abort_flag = d_abort;
   f.offset_width = ow;
   f.g8 = align_up(y.nseg[L], 8);

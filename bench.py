@@ -66,10 +66,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "aa7d8e6528312e4ebb9ef783ba8eba1a5bfc7b403254e2f5dda655280ea4713b",
-                       "fetch_kib": 6596420.5, "write_kib": 19401818.5},
-    "k_finish": {"sources_sha256": "aa7d8e6528312e4ebb9ef783ba8eba1a5bfc7b403254e2f5dda655280ea4713b",
-                 "fetch_kib": 27326413, "write_kib": 18596936},
+    "k_pass_scatter": {"sources_sha256": "b04e17f51bf5f382e15e3f304ae797927036c9bc6d1b611876956caf34a71673",
+                       "fetch_kib": 6547887.8, "write_kib": 18367644.8},
+    "k_finish": {"sources_sha256": "b04e17f51bf5f382e15e3f304ae797927036c9bc6d1b611876956caf34a71673",
+                 "fetch_kib": 27373057, "write_kib": 18591453},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

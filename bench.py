@@ -252,13 +252,20 @@ def bench_tiny(args):
         out = mgt.alloc_outputs(d, partitioned=part)
         ms = _timed(lambda: mgt.transpose(d, plan=plan, workspace=ws, partitioned=part, out=out),
                     max(args.steps, 50), 5)
-        h = {k: v.cpu().numpy() for k, v in out.items() if v is not None}
+        # the same call recorded once as a graph and replayed (one launch per call)
+        gout = mgt.alloc_outputs(d, partitioned=part)
+        g, gout, _ = mgt.transpose_graph(d, plan=plan, workspace=ws, partitioned=part, out=gout)
+        ms_g = _timed(g.launch, max(args.steps, 50), 5)
         ref = oracle.transpose(a)
-        exact = all(np.array_equal(h[k], getattr(ref, k)) for k in
-                    ("t_row_ptr", "t_col", "t_payload_off", "t_payload"))
-        res["partitioned" if part else "plain"] = {"us_per_call": ms * 1e3,
-                                                   "cells_per_s": a.nnz / (ms * 1e-3),
-                                                   "bit_exact": bool(exact)}
+
+        def exact(o):
+            h = {k: v.cpu().numpy() for k, v in o.items() if v is not None}
+            return bool(all(np.array_equal(h[k], getattr(ref, k)) for k in
+                            ("t_row_ptr", "t_col", "t_payload_off", "t_payload")))
+        res["partitioned" if part else "plain"] = {
+            "us_per_call": ms * 1e3, "cells_per_s": a.nnz / (ms * 1e-3), "bit_exact": exact(out),
+            "graph_us_per_call": ms_g * 1e3, "graph_bit_exact": exact(gout)}
+        g.close()
     print(json.dumps(res), flush=True)
 
 

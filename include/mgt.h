@@ -254,6 +254,34 @@ int mgt_batch_submit(mgt_plan_t batch_plan, const mgt_item* items, int32_t n_ite
                      void* workspace, size_t workspace_bytes, int32_t* d_status,
                      hipStream_t stream, hipEvent_t done);
 
+/* ------------------------------------------------------------------ graphs */
+
+/*
+ * A transpose recorded once and replayed: for callers that transpose many
+ * small matrices of a fixed shape into fixed buffers, where the host cost of
+ * one call (descriptor upload, one launch per stage) outweighs the kernels.
+ * The graph owns a pinned copy of the descriptor and every stage launch of
+ * one mgt_transpose (partitioned == 0) or mgt_transpose_partitioned
+ * (partitioned != 0) call with these exact pointers; arguments and errors are
+ * those of that call (plans with MGT_DEBUG_TIMING, batch or view plans give
+ * MGT_EINVAL). Nothing runs at creation. Each mgt_graph_launch runs the whole
+ * call on `stream`, reading the inputs as they are at that time; the buffers
+ * must stay allocated while the graph exists, and launches that overlap on
+ * one workspace race. The plan may be destroyed after creation. The graph
+ * clears its own status and counters with kernels (it records no memset).
+ */
+typedef struct mgt_graph_s* mgt_graph_t;
+
+int mgt_graph_create(mgt_plan_t plan, int32_t partitioned, const void* row_ptr,
+                     const int32_t* col, const void* payload_off, const uint8_t* payload,
+                     void* t_row_ptr, int32_t* t_col, void* t_payload_off, uint8_t* t_payload,
+                     uint32_t* perm, int64_t* xfer_cells, int64_t* xfer_bytes,
+                     int64_t* part_cell_off, int64_t* part_byte_off, int64_t* sdispls,
+                     int64_t* rdispls, void* workspace, size_t workspace_bytes,
+                     int32_t* d_status, mgt_graph_t* out);
+int mgt_graph_launch(mgt_graph_t graph, hipStream_t stream);
+int mgt_graph_destroy(mgt_graph_t graph);
+
 /* ------------------------------------------------------------------ utilities */
 
 /* Per-stage device times of the last call made with MGT_DEBUG_TIMING

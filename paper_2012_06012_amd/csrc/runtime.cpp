@@ -305,6 +305,11 @@ struct mgt_plan_s {
   size_t ws_view = 0;
 };
 
+struct mgt_graph_s {
+  hipGraphExec_t exec = nullptr;
+  void* staging = nullptr;  // pinned upload buffer the graph's copy node reads
+};
+
 namespace {
 
 int ensure_staging(mgt_plan_s* p, size_t bytes) {
@@ -352,17 +357,26 @@ struct ViewCall {
   int32_t op, column_view;
 };
 
+// Bytes of the item table and bounds uploaded at the start of a call.
+size_t upload_bytes(const Layout& y) {
+  return y.n_vbounds ? y.o_vbounds + 8ull * y.n_vbounds : y.o_bounds + 8ull * y.total_bounds;
+}
+
+// graph_staging: the call is being recorded into a graph that owns this
+// pinned upload buffer (its contents are read at every replay); the plan's
+// own staging buffer, completion event and stage timing are left alone.
 int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, int32_t* d_status,
-        hipStream_t s, const ViewCall* vc = nullptr) {
+        hipStream_t s, const ViewCall* vc = nullptr, void* graph_staging = nullptr) {
   uint8_t* W = (uint8_t*)ws;
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
   // 1. upload items + bounds through the pinned staging buffer
-  const size_t up_bytes = y.n_vbounds ? y.o_vbounds + 8ull * y.n_vbounds
-                                      : y.o_bounds + 8ull * y.total_bounds;
-  int st = ensure_staging(p, up_bytes);
-  if (st != MGT_OK) return st;
-  uint8_t* H = (uint8_t*)p->staging;
+  const size_t up_bytes = upload_bytes(y);
+  if (!graph_staging) {
+    int st = ensure_staging(p, up_bytes);
+    if (st != MGT_OK) return st;
+  }
+  uint8_t* H = (uint8_t*)(graph_staging ? graph_staging : p->staging);
   int64_t* hb = (int64_t*)(H + y.o_bounds);
   uint64_t bo = 0;
   for (uint32_t i = 0; i < n; ++i) {
@@ -390,8 +404,10 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   if (vc) std::memcpy(H + y.o_vbounds, vc->bounds, 8ull * y.n_vbounds);
   time_mark(p, s, "start");
   MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
-  MGT_HIP(hipEventRecord(p->upload_done, s));
-  p->upload_pending = true;
+  if (!graph_staging) {
+    MGT_HIP(hipEventRecord(p->upload_done, s));
+    p->upload_pending = true;
+  }
 
   const ItemDev* d_items = (const ItemDev*)(W + y.o_items);
   int32_t* d_item_status = (int32_t*)(W + y.o_status);
@@ -548,11 +564,39 @@ int check_io(const mgt_desc& d, uint32_t flags, const void* row_ptr, const int32
   return MGT_OK;
 }
 
+// Records one call into g: the pinned upload buffer and a private stream are
+// made first (nothing is allocated while capturing), then the call is
+// captured on that stream and instantiated.
+int record_graph(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws,
+                 int32_t* d_status, mgt_graph_s* g) {
+  if (hipHostMalloc(&g->staging, upload_bytes(y), hipHostMallocDefault) != hipSuccess) {
+    g->staging = nullptr;
+    return MGT_ENOMEM;
+  }
+  hipStream_t s = nullptr;
+  if (hipStreamCreate(&s) != hipSuccess) return MGT_EHIP;
+  hipGraph_t graph = nullptr;
+  int st = MGT_OK;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) st = MGT_EHIP;
+  if (st == MGT_OK) {
+    st = run(p, items, y, ws, d_status, s, nullptr, g->staging);
+    // the capture is ended whatever happened inside it
+    if (hipStreamEndCapture(s, &graph) != hipSuccess && st == MGT_OK) st = MGT_EHIP;
+  }
+  if (st == MGT_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    g->exec = nullptr;
+    st = MGT_EHIP;
+  }
+  if (graph) hipGraphDestroy(graph);
+  hipStreamDestroy(s);
+  return st;
+}
+
 int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int32_t* col,
                 const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,
                 void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xc, int64_t* xb,
                 int64_t* pco, int64_t* pbo, int64_t* sd, int64_t* rd, void* ws, size_t ws_bytes,
-                int32_t* d_status, hipStream_t s) {
+                int32_t* d_status, hipStream_t s, mgt_graph_s* graph = nullptr) {
   if (!p || p->batch || p->view_op >= 0) return MGT_EINVAL;
   const mgt_desc& d = p->desc;
   int st = check_io(d, p->flags, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
@@ -579,6 +623,7 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   if (!partitioned) it.bounds = nullptr;
   Layout y = make_layout(items);
   if (ws_bytes < y.bytes) return MGT_ENOMEM;
+  if (graph) return record_graph(p, items, y, ws, d_status, graph);
   p->timing.used = 0;
   return run(p, items, y, ws, d_status, s);
 }
@@ -764,6 +809,44 @@ int mgt_view_transform(mgt_plan_t p, const void* row_ptr, const int32_t* col,
   ViewCall vc{col, p->bounds.data(), p->desc.n_rows, p->desc.n_cols, p->view_op, p->column_view};
   p->timing.used = 0;
   return run(p, items, y, workspace, d_status, stream, &vc);
+}
+
+int mgt_graph_create(mgt_plan_t plan, int32_t partitioned, const void* row_ptr, const int32_t* col,
+                     const void* payload_off, const uint8_t* payload, void* t_row_ptr,
+                     int32_t* t_col, void* t_payload_off, uint8_t* t_payload, uint32_t* perm,
+                     int64_t* xfer_cells, int64_t* xfer_bytes, int64_t* part_cell_off,
+                     int64_t* part_byte_off, int64_t* sdispls, int64_t* rdispls, void* workspace,
+                     size_t workspace_bytes, int32_t* d_status, mgt_graph_t* out) {
+  if (!plan || !out || plan->batch || plan->view_op >= 0) return MGT_EINVAL;
+  if (plan->flags & MGT_DEBUG_TIMING) return MGT_EINVAL;
+  if (partitioned && plan->desc.n_parts > 1 && plan->desc.n_rows != plan->desc.n_cols)
+    return MGT_EINVAL;
+  mgt_graph_s* g = new (std::nothrow) mgt_graph_s();
+  if (!g) return MGT_ENOMEM;
+  int st = single_call(plan, partitioned != 0, row_ptr, col, payload_off, payload, t_row_ptr,
+                       t_col, t_payload_off, t_payload, perm, xfer_cells, xfer_bytes,
+                       part_cell_off, part_byte_off, sdispls, rdispls, workspace,
+                       workspace_bytes, d_status, nullptr, g);
+  if (st == MGT_OK && !g->exec) st = MGT_EINVAL;
+  if (st != MGT_OK) {
+    mgt_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return MGT_OK;
+}
+
+int mgt_graph_launch(mgt_graph_t g, hipStream_t stream) {
+  if (!g || !g->exec) return MGT_EINVAL;
+  return hipGraphLaunch(g->exec, stream) == hipSuccess ? MGT_OK : MGT_EHIP;
+}
+
+int mgt_graph_destroy(mgt_graph_t g) {
+  if (!g) return MGT_EINVAL;
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->staging) hipHostFree(g->staging);
+  delete g;
+  return MGT_OK;
 }
 
 int mgt_batch_plan(const mgt_batch_limits* lim, mgt_plan_t* out, size_t* workspace_bytes) {

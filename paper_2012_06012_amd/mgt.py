@@ -76,15 +76,20 @@ _lib.mgt_plan_stage_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_float),
 _lib.mgt_view_plan.argtypes = [ctypes.POINTER(Desc), _i32, _i32, ctypes.POINTER(_vp),
                                ctypes.POINTER(_sz)]
 _lib.mgt_view_transform.argtypes = [_vp] * 10 + [_vp, _sz, _vp, _vp]
+_lib.mgt_graph_create.argtypes = [_vp, _i32] + [_vp] * 16 + [_sz, _vp, ctypes.POINTER(_vp)]
+_lib.mgt_graph_launch.argtypes = [_vp, _vp]
+_lib.mgt_graph_destroy.argtypes = [_vp]
 _lib.mgt_version.restype = ctypes.c_char_p
 for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
-           "mgt_view_plan", "mgt_view_transform"):
+           "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
+           "mgt_graph_destroy"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
             "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
-            "mgt_version", "mgt_view_plan", "mgt_view_transform")
+            "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
+            "mgt_graph_launch", "mgt_graph_destroy")
 
 
 def version() -> str:
@@ -184,6 +189,45 @@ def mgt_transpose_partitioned(plan: Plan, row_ptr, col, payload_off, payload, t_
         _ptr(xfer_bytes), _ptr(part_cell_off), _ptr(part_byte_off), _ptr(sdispls), _ptr(rdispls),
         _ptr(workspace), workspace.numel() * workspace.element_size(), _ptr(d_status),
         _stream(stream)), "mgt_transpose_partitioned")
+
+
+class Graph:
+    """Owns an mgt graph: one recorded transpose call, replayed by launch().
+
+    Keeps the tensors it was recorded with alive for as long as it exists."""
+
+    def __init__(self, handle: int, keep: tuple):
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, stream=None) -> None:
+        _check(_lib.mgt_graph_launch(self.handle, _stream(stream)), "mgt_graph_launch")
+
+    def close(self):
+        if self.handle:
+            _lib.mgt_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mgt_graph_create(plan: Plan, partitioned: bool, row_ptr, col, payload_off, payload,
+                     t_row_ptr, t_col, t_payload_off, t_payload, perm, xfer_cells, xfer_bytes,
+                     part_cell_off, part_byte_off, sdispls, rdispls, workspace,
+                     d_status=None) -> Graph:
+    args = (row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off, t_payload, perm,
+            xfer_cells, xfer_bytes, part_cell_off, part_byte_off, sdispls, rdispls, workspace,
+            d_status)
+    h = _vp()
+    _check(_lib.mgt_graph_create(
+        plan.handle, 1 if partitioned else 0, *[_ptr(t) for t in args[:16]],
+        workspace.numel() * workspace.element_size(), _ptr(d_status), ctypes.byref(h)),
+        "mgt_graph_create")
+    return Graph(h.value, args)
 
 
 def mgt_view_plan(n_rows: int, n_cols: int, nnz: int, payload_bytes: int, offset_width: int,
@@ -329,6 +373,29 @@ def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: b
                       out["t_col"], out["t_payload_off"], out["t_payload"], out["perm"],
                       workspace, status, stream)
     return out, status
+
+
+def transpose_graph(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: bool = False,
+                    partitioned: bool = False, validate: bool = False, out=None):
+    """Records the transpose of a into fixed outputs as a graph.
+
+    Returns (Graph, outputs dict, status tensor); every Graph.launch() writes
+    the transpose of a's current contents into the same outputs."""
+    flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+    if plan is None:
+        plan = plan_for(a, flags)
+    dev = a.col.device
+    if workspace is None:
+        workspace = workspace_for(plan, dev)
+    if out is None:
+        out = alloc_outputs(a, perm, partitioned, dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    g = mgt_graph_create(plan, partitioned, a.row_ptr, a.col, a.payload_off, a.payload,
+                         out["t_row_ptr"], out["t_col"], out["t_payload_off"], out["t_payload"],
+                         out["perm"], out.get("xfer_cells"), out.get("xfer_bytes"),
+                         out.get("part_cell_off"), out.get("part_byte_off"), out.get("sdispls"),
+                         out.get("rdispls"), workspace, status)
+    return g, out, status
 
 
 def batch_entries(mats: Sequence[DeviceCsr], outs: Sequence[dict], perm: bool = False,

@@ -175,6 +175,32 @@ def test_partitioned_rejects_missing_outputs():
     assert rc == -1
 
 
+def test_graph_create_rejects_before_recording():
+    mgt = _lib()
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    lib.mgt_graph_create.argtypes = [ctypes.c_void_p, ctypes.c_int32] + [ctypes.c_void_p] * 16 + [
+        ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.mgt_graph_launch.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.mgt_graph_destroy.argtypes = [ctypes.c_void_p]
+    fake = ctypes.c_void_p(4096)
+    g = ctypes.c_void_p()
+
+    def create(plan, part=0, col=fake, out=True):
+        return lib.mgt_graph_create(plan, part, fake, col, fake, None, fake, fake, fake, None,
+                                    None, fake, fake, fake, fake, None, None, fake, 1 << 30, None,
+                                    ctypes.byref(g) if out else None)
+
+    assert create(None) == -1
+    assert create(mgt.mgt_plan(10, 10, 5, 0, 8, None).handle, out=False) == -1
+    assert create(mgt.mgt_plan(10, 10, 5, 0, 8, None).handle, col=None) == -1   # missing col
+    assert create(mgt.mgt_plan(10, 10, 5, 0, 8, None, flags=mgt.DEBUG_TIMING).handle) == -1
+    assert create(mgt.mgt_view_plan(10, 10, 5, 0, 8, None, mgt.VIEW_SWAP,
+                                    mgt.ROW_VIEW).handle) == -1
+    assert g.value is None
+    assert lib.mgt_graph_launch(None, None) == -1
+    assert lib.mgt_graph_destroy(None) == -1
+
+
 def test_batch_plan_limits_and_exact_workspace():
     mgt = _lib()
     with pytest.raises(mgt.MgtError):

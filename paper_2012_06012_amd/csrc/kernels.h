@@ -108,10 +108,8 @@ hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
-hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* abort_flag,
-                        int32_t offset_width, hipStream_t s);
-hipError_t launch_status_out(const int32_t* item_status, const int32_t* abort_flag,
-                             uint32_t n_items, int32_t* d_status, hipStream_t s);
+hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,
+                        const int32_t* abort_flag, int32_t ow, int32_t* d_status, hipStream_t s);
 
 // Scratch needed by launch_scan for n_max elements (bytes).
 inline uint64_t scan_scratch_bytes(uint64_t n_max) {

@@ -276,6 +276,45 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* in0, uint6
   }
 }
 
+// The three kernels above in one workgroup, for arrays of at most
+// kSmallScan entries: the carry runs through the kScanBlock chunks in order,
+// which costs less than two more launches while the array is this short.
+constexpr uint64_t kSmallScan = 4 * (uint64_t)kScanBlock;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t* in0, uint64_t* out0,
+                                                     const uint32_t* in1, uint64_t* out1,
+                                                     const uint64_t* n_dev, uint64_t n_max) {
+  __shared__ uint64_t red[1024 / kWave + 1];
+  constexpr int kPer = kScanBlock / 1024;
+  const uint64_t n = n_dev ? min(*n_dev, n_max) : n_max;
+  for (int arr = 0; arr < (out1 ? 2 : 1); ++arr) {
+    const uint32_t* in = arr ? in1 : in0;
+    uint64_t* out = arr ? out1 : out0;
+    uint64_t carry = 0;
+    for (uint64_t lo = 0; lo < n; lo += kScanBlock) {
+      const uint64_t t0 = lo + (uint64_t)threadIdx.x * kPer;
+      uint32_t v[kPer];
+      uint64_t sum = 0;
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        v[j] = (in && t0 + j < n) ? in[t0 + j] : 0u;
+        sum += v[j];
+      }
+      uint64_t tot;
+      uint64_t ex = block_excl_scan<1024 / kWave>(sum, red, tot) + carry;
+      if (in) {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+          if (t0 + j < n) out[t0 + j] = ex;
+          ex += v[j];
+        }
+      }
+      carry += tot;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+  }
+}
+
 // ----------------------------------------------------------------------------- pass: histogram
 
 constexpr int kBatch = 8;  // independent loads in flight per lane
@@ -1348,9 +1387,14 @@ __global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
 
 // ----------------------------------------------------------------------------- tails
 
-__global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int32_t* abort_flag,
-                                                int ow) {
+__global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int32_t* item_status,
+                                                const int32_t* abort_flag, int ow,
+                                                int32_t* d_status) {
   __shared__ uint64_t red[1024 / kWave + 1];
+  if (d_status && threadIdx.x == 0) {  // the caller's status word of this item
+    const int32_t st = item_status[blockIdx.x];
+    d_status[blockIdx.x] = (st == MGT_OK && *abort_flag) ? MGT_ECANCELED : st;
+  }
   if (aborted(abort_flag)) return;
   const ItemDev& it = items[blockIdx.x];
   if (threadIdx.x == 0) {
@@ -1394,14 +1438,6 @@ __global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int3
   }
 }
 
-__global__ void k_status_out(const int32_t* item_status, const int32_t* abort_flag, uint32_t n,
-                             int32_t* d_status) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int32_t s = item_status[i];
-  d_status[i] = (s == MGT_OK && *abort_flag) ? MGT_ECANCELED : s;
-}
-
 // ----------------------------------------------------------------------------- launchers
 
 static inline dim3 grid1(uint64_t n) { return dim3((unsigned)n); }
@@ -1425,6 +1461,11 @@ hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_
 
 hipError_t launch_scan(const uint32_t* in0, uint64_t* out0, const uint32_t* in1, uint64_t* out1,
                        const uint64_t* n_dev, uint64_t n_max, uint64_t* block_sums, hipStream_t s) {
+  if (n_max <= kSmallScan) {
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in0, out0, in1, out1, n_dev,
+                       n_max);
+    return hipGetLastError();
+  }
   const uint64_t nb = (n_max + kScanBlock - 1) / kScanBlock;
   const uint64_t cap = nb + 1;
   if (nb) {
@@ -1478,16 +1519,10 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* abort_flag,
-                        int32_t ow, hipStream_t s) {
-  hipLaunchKernelGGL(k_tails, grid1(n_items), dim3(1024), 0, s, items, abort_flag, ow);
-  return hipGetLastError();
-}
-
-hipError_t launch_status_out(const int32_t* item_status, const int32_t* abort_flag,
-                             uint32_t n_items, int32_t* d_status, hipStream_t s) {
-  hipLaunchKernelGGL(k_status_out, dim3((n_items + 255) / 256), dim3(256), 0, s, item_status,
-                     abort_flag, n_items, d_status);
+hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,
+                        const int32_t* abort_flag, int32_t ow, int32_t* d_status, hipStream_t s) {
+  hipLaunchKernelGGL(k_tails, grid1(n_items), dim3(1024), 0, s, items, item_status, abort_flag, ow,
+                     d_status);
   return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ using namespace mgt;
 namespace {
 
 constexpr uint32_t kTileCells = 16384;    // cells per partition-pass tile (multiple of kSub)
+constexpr uint64_t kTargetTiles = 1024;   // tiles a single-matrix pass aims for
+constexpr uint64_t kTargetBuckets = 512;  // finish buckets a small single-matrix call aims for
 constexpr int kMaxBitsPerPass = kMaxPassBits;  // fan-out 256 per bits-mode pass
 constexpr uint32_t kMaxPartFanout = 512;  // preferred fan-out of the partition pass
 constexpr int kMaxItems = 65535;
@@ -68,8 +70,12 @@ int passes_for(int B, int first_cap, int mb) {
   return 1 + (rest + mb - 1) / mb;
 }
 
+// spread: a single-matrix call, whose finish buckets shrink (down to kSub / 8
+// cells) on small matrices so that about kTargetBuckets workgroups share the
+// finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
+// parallelism.
 Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
-                    int mb, int mf) {
+                    int mb, int mf, bool spread) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -83,7 +89,10 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
   int fb_ideal = 0;
   if (nnz > 0 && n_cols > 0) {
     const double per_col = (double)nnz / (double)n_cols;
-    fb_ideal = floor_log2_u64((uint64_t)std::max(1.0, 2.0 * kSub / per_col));
+    double target = 2.0 * kSub;
+    if (spread)
+      target = std::min(target, std::max(kSub / 8.0, (double)nnz / (double)kTargetBuckets));
+    fb_ideal = floor_log2_u64((uint64_t)std::max(1.0, target / per_col));
   } else {
     fb_ideal = mf;
   }
@@ -113,10 +122,12 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
   return s;
 }
 
-Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned) {
-  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, max_pass_bits(), max_finish_bits());
+Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
+                 bool spread) {
+  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, max_pass_bits(), max_finish_bits(),
+                          spread);
   if (s.n_levels > kMaxLevels)
-    s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, kMaxBitsPerPass, kMaxFinishBits);
+    s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, kMaxBitsPerPass, kMaxFinishBits, spread);
   return s;
 }
 
@@ -148,8 +159,21 @@ struct Layout {
   uint64_t o_ks[2], o_rk[2], o_pay[2], o_rso = 0;
   // view operations: partition bounds of the matrix, per-cell keys and values
   uint64_t n_vbounds = 0, o_vbounds = 0, o_vkeys = 0, o_vvals = 0;
+  uint32_t tile_cells = kTileCells;
   uint64_t bytes = 0;
 };
+
+// Cells per partition-pass tile of a single-matrix call: the smallest power
+// of two from kSub up that keeps the tile count near kTargetTiles, at most
+// kTileCells. Small matrices thus spread over many workgroups instead of
+// running a few long tiles one sub-chunk after another. Batches keep
+// kTileCells (their items already give many tiles, and their workspace
+// estimate must bound every batch within the limits).
+uint32_t tile_cells_for(uint64_t nnz) {
+  uint32_t t = kSub;
+  while (t < kTileCells && (nnz + t - 1) / t > kTargetTiles) t *= 2;
+  return t;
+}
 
 // n_vbounds > 0: a view operation on the single item, whose matrix has
 // n_vbounds - 1 partitions.
@@ -157,6 +181,8 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   Layout y;
   y.n_vbounds = n_vbounds;
   y.n_items = (uint32_t)items.size();
+  if (items.size() == 1) y.tile_cells = tile_cells_for((uint64_t)items[0].d.nnz);
+  const uint64_t tc = y.tile_cells;
   int L = 1;
   for (auto& it : items) L = std::max(L, it.s.n_levels);
   y.L = L;
@@ -183,7 +209,7 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
       y.nseg[l] += ns;
       if (l < L) ns *= fanout(it.s, l, it.d.n_parts);
     }
-    const uint64_t t0 = ((uint64_t)it.d.nnz + kTileCells - 1) / kTileCells;
+    const uint64_t t0 = ((uint64_t)it.d.nnz + tc - 1) / tc;
     it.dev.tile_base = tiles0;
     tiles0 += t0;
   }
@@ -195,7 +221,7 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
       (void)ns;
       uint64_t segs_item = 1;
       for (int q = 0; q < l; ++q) segs_item *= fanout(it.s, q, it.d.n_parts);
-      const uint64_t t = ((uint64_t)it.d.nnz + kTileCells - 1) / kTileCells + (l ? segs_item : 0);
+      const uint64_t t = ((uint64_t)it.d.nnz + tc - 1) / tc + (l ? segs_item : 0);
       tiles += t;
       hist += t * fanout(it.s, l, it.d.n_parts);
     }
@@ -425,7 +451,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   uint64_t* tsrc = (uint64_t*)(W + y.o_tsrc);
   uint64_t* scan = (uint64_t*)(W + y.o_scan);
 
-  MGT_HIP(launch_init(d_items, n, segs(0), tcnt(0), hsz(0), d_item_status, d_abort, kTileCells, s));
+  MGT_HIP(launch_init(d_items, n, segs(0), tcnt(0), hsz(0), d_item_status, d_abort, y.tile_cells, s));
   if (vc) {
     ViewArgs v{};
     v.items = d_items;
@@ -484,7 +510,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.item_status = d_item_status;
     a.abort_flag = d_abort;
     a.g8 = align_up(y.tiles_max[l], 8);
-    a.tile_cells = kTileCells;
+    a.tile_cells = y.tile_cells;
     a.offset_width = ow;
     a.has_val = (vc && l == 0) ? 1 : 0;
     MGT_HIP(launch_pass_hist(a, s));
@@ -504,7 +530,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     c.children = segs(l + 1);
     c.child_tiles = (l + 1 < L) ? tcnt(l + 1) : nullptr;
     c.child_hsize = (l + 1 < L) ? hsz(l + 1) : nullptr;
-    c.tile_cells = kTileCells;
+    c.tile_cells = y.tile_cells;
     c.abort_flag = d_abort;
     MGT_HIP(launch_children(c, s));
     if (l + 1 < L)
@@ -528,8 +554,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.g8 = align_up(y.nseg[L], 8);
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
-  MGT_HIP(launch_tails(d_items, n, d_abort, ow, s));
-  if (d_status) MGT_HIP(launch_status_out(d_item_status, d_abort, n, d_status, s));
+  MGT_HIP(launch_tails(d_items, n, d_item_status, d_abort, ow, d_status, s));
   time_mark(p, s, "tails");
   return MGT_OK;
 }
@@ -608,7 +633,7 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   HostItem& it = items[0];
   it.d = d;
   it.bounds = p->bounds.empty() ? nullptr : p->bounds.data();
-  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned);
+  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned, true);
   if (!partitioned) it.d.n_parts = 1;
   fill_outputs(it.dev, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off, t_payload,
                perm);
@@ -633,7 +658,7 @@ size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned) {
   items[0].d = d;
   if (!partitioned) items[0].d.n_parts = 1;
   items[0].bounds = bounds;
-  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned);
+  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned, true);
   std::memset(&items[0].dev, 0, sizeof(ItemDev));
   return make_layout(items).bytes;
 }
@@ -662,7 +687,7 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
     HostItem& it = items[(size_t)i];
     it.d = m.desc;
     it.bounds = m.desc.part_bounds;
-    it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.n_parts, m.desc.part_bounds, part);
+    it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.n_parts, m.desc.part_bounds, part, false);
     fill_outputs(it.dev, m.row_ptr, m.col, m.payload_off, m.payload, m.t_row_ptr, m.t_col,
                  m.t_payload_off, m.t_payload, m.perm);
     if (part) {
@@ -775,7 +800,7 @@ int mgt_view_plan(const mgt_desc* desc, int32_t op, int32_t in_view, mgt_plan_t*
   std::vector<HostItem> items(1);
   items[0].d = v;
   items[0].bounds = nullptr;
-  items[0].s = make_sched(v.n_cols, v.nnz, 1, nullptr, false);
+  items[0].s = make_sched(v.n_cols, v.nnz, 1, nullptr, false, true);
   std::memset(&items[0].dev, 0, sizeof(ItemDev));
   p->ws_view = make_layout(items, (uint64_t)R + 1).bytes;
   *out = p;
@@ -798,7 +823,7 @@ int mgt_view_transform(mgt_plan_t p, const void* row_ptr, const int32_t* col,
   HostItem& it = items[0];
   it.d = v;
   it.bounds = nullptr;
-  it.s = make_sched(v.n_cols, v.nnz, 1, nullptr, false);
+  it.s = make_sched(v.n_cols, v.nnz, 1, nullptr, false, true);
   fill_outputs(it.dev, row_ptr, col, payload_off, payload, o_row_ptr, o_col, o_payload_off,
                o_payload, perm);
   Layout y = make_layout(items, p->bounds.size());

@@ -66,10 +66,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "b04e17f51bf5f382e15e3f304ae797927036c9bc6d1b611876956caf34a71673",
-                       "fetch_kib": 6547887.8, "write_kib": 18367644.8},
-    "k_finish": {"sources_sha256": "b04e17f51bf5f382e15e3f304ae797927036c9bc6d1b611876956caf34a71673",
-                 "fetch_kib": 27373057, "write_kib": 18591453},
+    "k_pass_scatter": {"sources_sha256": "d3959dc63ec4e642989ac9d2be12129773c9fedc3eccceb2f02208cdbd78f579",
+                       "fetch_kib": 6549164.7, "write_kib": 18367803.2},
+    "k_finish": {"sources_sha256": "d3959dc63ec4e642989ac9d2be12129773c9fedc3eccceb2f02208cdbd78f579",
+                 "fetch_kib": 27363958, "write_kib": 18591312},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

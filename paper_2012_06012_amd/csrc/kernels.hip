@@ -50,6 +50,28 @@ __device__ __forceinline__ void add_u64(uint64_t* p, uint64_t v) {
                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Adds every active lane's cell (one cell of z bytes) to xc[key] and xb[key]
+// with one atomic pair per distinct key in the wave: the lanes holding the
+// leader's key are summed first. Sorted cells give a wave one or two keys.
+// Called by whole waves (uniform control flow).
+__device__ __forceinline__ void wave_add_xfer(bool active, uint32_t key, uint32_t z, uint64_t* xc,
+                                              uint64_t* xb) {
+  uint64_t left = ballot(active);
+  while (left) {
+    const int leader = __ffsll((unsigned long long)left) - 1;
+    const uint32_t k = wave_bcast(key, leader);
+    const bool mine = active && key == k;
+    const uint64_t same = ballot(mine);
+    const uint64_t incl = wave_incl_scan_u64(mine ? (uint64_t)z : 0ull);
+    const uint64_t bytes = wave_bcast(incl, kWave - 1);
+    if ((int)lane_id() == leader) {
+      add_u64(&xc[k], (uint64_t)__popcll(same));
+      add_u64(&xb[k], bytes);
+    }
+    left &= ~same;
+  }
+}
+
 __device__ __forceinline__ int ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
 __device__ __forceinline__ uint32_t seg_fanout(const Seg& s, uint32_t R) {
@@ -1049,13 +1071,14 @@ __global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArg
           const uint64_t cd = cdst[q];
           a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
           a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
-          if (xfer_per_cell) {
-            const uint32_t d = L.dig[i];
+        }
+        if (xfer_per_cell) {  // the sub-chunk spans source partitions (uniform)
+          uint32_t key = 0;
+          if (i < n) {
             const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
-            const uint32_t dp = d >> sg.bits;
-            add_u64((uint64_t*)&it->xfer_cells[(uint64_t)sp * R + dp], 1ull);
-            add_u64((uint64_t*)&it->xfer_bytes[(uint64_t)sp * R + dp], (uint64_t)pz[q]);
+            key = sp * R + (L.dig[i] >> sg.bits);
           }
+          wave_add_xfer(i < n, key, pz[q], (uint64_t*)it->xfer_cells, (uint64_t*)it->xfer_bytes);
         }
       }
       pay_store(P, pd, ps, pz);

@@ -53,6 +53,9 @@ def test_hetero_recipe_scaled(scale):
     (4, 4096, 4096, 30.0, 4, 4, 4, True, 16),
     (5, 777, 777, 50.0, 0, 5, 8, True, 5),
     (6, 20000, 20000, 4.0, 0, 9, 8, True, 64),
+    # four rows per partition: every wave of a sub-chunk holds many
+    # (source, destination) partition pairs of the transfer matrices
+    (7, 4096, 4096, 8.0, 0, 9, 8, False, 1024),
 ])
 def test_random_shapes(seed, n_rows, n_cols, deg, wlo, whi, ow, sort_rows, parts):
     a = gen.random_small(seed, n_rows=n_rows, n_cols=n_cols, deg_mean=deg, w_lo=wlo, w_hi=whi,

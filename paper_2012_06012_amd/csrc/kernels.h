@@ -10,6 +10,11 @@ namespace mgt {
 // Geometry shared by host and device.
 constexpr int kBlock = 256;         // threads per workgroup (4 wave64)
 constexpr int kSub = 2048;          // cells sorted in LDS at once
+// Geometry of the records-only partition pass when its tiles hold at least
+// kWideSub cells: twice the cells per LDS sort, so each digit's run of
+// records is twice as long (kernels_wide.hip).
+constexpr int kWideBlock = 512;
+constexpr int kWideSub = 4096;
 constexpr int kMaxPassBits = 8;     // digit bits of a bits-mode pass (fan-out 256)
 constexpr int kScanBlock = 4096;    // elements per scan workgroup
 
@@ -106,6 +111,7 @@ struct ViewArgs {
 hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s);
 hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
+hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s);  // records-only pass
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,

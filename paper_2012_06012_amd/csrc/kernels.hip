@@ -11,8 +11,21 @@
 #include "kernels.h"
 #include "prims.h"
 
-namespace mgt {
+// Workgroup geometry of this copy of the device code. The library holds two:
+// 256 threads and 2,048-cell sub-chunks for every stage (this file), and 512
+// threads and 4,096-cell sub-chunks for the records-only pass alone
+// (kernels_wide.hip, which includes this file in a namespace of its own).
+#ifndef MGT_GEO_NS
+#define MGT_GEO_NS geo256
+#define MGT_GEO_BLOCK ::mgt::kBlock
+#define MGT_GEO_SUB ::mgt::kSub
+#endif
 
+namespace mgt {
+namespace MGT_GEO_NS {
+
+constexpr int kBlock = MGT_GEO_BLOCK;      // threads per workgroup
+constexpr int kSub = MGT_GEO_SUB;          // cells sorted in LDS at once
 constexpr int kNW = kBlock / kWave;        // waves per workgroup
 constexpr int kItems = kSub / kBlock;      // cells per lane per sub-chunk
 constexpr int kWaveCells = kSub / kNW;     // cells of one wave per sub-chunk
@@ -881,7 +894,7 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
 // kVal (first pass only): every cell carries a value of its own (item vval)
 // in place of its row id, so no rows are expanded.
 template <bool kPass0, bool kDefer, bool kVal>
-__global__ __launch_bounds__(kBlock, kDefer ? 3 : 2) void k_pass_scatter(PassArgs a) {
+__global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scatter(PassArgs a) {
   constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
   __shared__ SortLdsT<kFan, !kDefer> L;
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
@@ -1461,92 +1474,108 @@ __global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int3
   }
 }
 
+}  // namespace MGT_GEO_NS
+
 // ----------------------------------------------------------------------------- launchers
+
+namespace G = MGT_GEO_NS;
 
 static inline dim3 grid1(uint64_t n) { return dim3((unsigned)n); }
 
+#ifdef MGT_WIDE
+hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s) {
+  if (a.g8)
+    hipLaunchKernelGGL((G::k_pass_scatter<false, true, false>), grid1(a.g8), dim3(G::kBlock), 0, s,
+                       a);
+  return hipGetLastError();
+}
+#else
 hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,
                        uint32_t* hsize0, int32_t* item_status, int32_t* abort_flag,
                        uint32_t tile_cells, hipStream_t s) {
-  hipLaunchKernelGGL(k_init, grid1(n_items), dim3(kBlock), 0, s, items, n_items, segs0, tiles0,
+  hipLaunchKernelGGL(G::k_init, grid1(n_items), dim3(G::kBlock), 0, s, items, n_items, segs0, tiles0,
                      hsize0, item_status, abort_flag, tile_cells);
   return hipGetLastError();
 }
 
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
                            int32_t* item_status, int32_t* abort_flag, int32_t ow, hipStream_t s) {
-  uint64_t gx = (max_len + 1 + kBlock * 16 - 1) / (kBlock * 16);
+  uint64_t gx = (max_len + 1 + G::kBlock * 16 - 1) / (G::kBlock * 16);
   gx = gx < 1 ? 1 : (gx > 2048 ? 2048 : gx);
-  hipLaunchKernelGGL(k_validate, dim3((unsigned)gx, n_items), dim3(kBlock), 0, s, items,
+  hipLaunchKernelGGL(G::k_validate, dim3((unsigned)gx, n_items), dim3(G::kBlock), 0, s, items,
                      item_status, abort_flag, ow);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* in0, uint64_t* out0, const uint32_t* in1, uint64_t* out1,
                        const uint64_t* n_dev, uint64_t n_max, uint64_t* block_sums, hipStream_t s) {
-  if (n_max <= kSmallScan) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in0, out0, in1, out1, n_dev,
+  if (n_max <= G::kSmallScan) {
+    hipLaunchKernelGGL(G::k_scan_small, dim3(1), dim3(1024), 0, s, in0, out0, in1, out1, n_dev,
                        n_max);
     return hipGetLastError();
   }
   const uint64_t nb = (n_max + kScanBlock - 1) / kScanBlock;
   const uint64_t cap = nb + 1;
   if (nb) {
-    hipLaunchKernelGGL(k_scan_reduce, grid1(nb), dim3(kBlock), 0, s, in0, in1, n_dev, n_max,
+    hipLaunchKernelGGL(G::k_scan_reduce, grid1(nb), dim3(G::kBlock), 0, s, in0, in1, n_dev, n_max,
                        block_sums, cap);
   }
-  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, s, n_dev, n_max, block_sums, cap, out0,
+  hipLaunchKernelGGL(G::k_scan_spine, dim3(1), dim3(1024), 0, s, n_dev, n_max, block_sums, cap, out0,
                      out1);
   if (nb) {
-    hipLaunchKernelGGL(k_scan_down, grid1(nb), dim3(kBlock), 0, s, in0, out0, in1, out1, n_dev,
+    hipLaunchKernelGGL(G::k_scan_down, grid1(nb), dim3(G::kBlock), 0, s, in0, out0, in1, out1, n_dev,
                        n_max, block_sums, cap);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s) {
-  if (a.g8) hipLaunchKernelGGL(k_pass_hist, grid1(a.g8), dim3(kBlock), 0, s, a);
+  if (a.g8) hipLaunchKernelGGL(G::k_pass_hist, grid1(a.g8), dim3(G::kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
   if (a.g8) {
     if (a.pass == 0 && a.has_val)
-      hipLaunchKernelGGL((k_pass_scatter<true, false, true>), grid1(a.g8), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((G::k_pass_scatter<true, false, true>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
     else if (a.pass == 0)
-      hipLaunchKernelGGL((k_pass_scatter<true, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((G::k_pass_scatter<true, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
+    else if (a.rso_out && a.tile_cells >= (uint32_t)kWideSub)
+      return launch_pass_scatter_wide(a, s);
     else if (a.rso_out)
-      hipLaunchKernelGGL((k_pass_scatter<false, true, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((G::k_pass_scatter<false, true, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
     else
-      hipLaunchKernelGGL((k_pass_scatter<false, false, false>), grid1(a.g8), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((G::k_pass_scatter<false, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s) {
-  const uint64_t nb = (a.nnz + kSub - 1) / kSub;
-  if (nb) hipLaunchKernelGGL(k_view_keys, grid1(nb), dim3(kBlock), 0, s, a);
+  const uint64_t nb = (a.nnz + G::kSub - 1) / G::kSub;
+  if (nb) hipLaunchKernelGGL(G::k_view_keys, grid1(nb), dim3(G::kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
-  if (a.nseg) hipLaunchKernelGGL(k_children, grid1(a.nseg), dim3(kBlock), 0, s, a);
+  if (a.nseg) hipLaunchKernelGGL(G::k_children, grid1(a.nseg), dim3(G::kBlock), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
   if (a.nbuckets) {
-    if (a.rso_in) hipLaunchKernelGGL(k_finish<true>, grid1(a.g8), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL(k_finish<false>, grid1(a.g8), dim3(kBlock), 0, s, a);
+    if (a.rso_in) hipLaunchKernelGGL(G::k_finish<true>, grid1(a.g8), dim3(G::kBlock), 0, s, a);
+    else hipLaunchKernelGGL(G::k_finish<false>, grid1(a.g8), dim3(G::kBlock), 0, s, a);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,
                         const int32_t* abort_flag, int32_t ow, int32_t* d_status, hipStream_t s) {
-  hipLaunchKernelGGL(k_tails, grid1(n_items), dim3(1024), 0, s, items, item_status, abort_flag, ow,
+  hipLaunchKernelGGL(G::k_tails, grid1(n_items), dim3(1024), 0, s, items, item_status, abort_flag, ow,
                      d_status);
   return hipGetLastError();
 }
+
+#endif  // MGT_WIDE
 
 }  // namespace mgt

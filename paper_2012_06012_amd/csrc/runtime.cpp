@@ -513,6 +513,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.tile_cells = y.tile_cells;
     a.offset_width = ow;
     a.has_val = (vc && l == 0) ? 1 : 0;
+    a.allow_wide = n == 1 ? 1 : 0;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];

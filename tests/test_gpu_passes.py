@@ -90,3 +90,11 @@ def test_batch_mixed_schedule_lengths(monkeypatch):
     assert (status.cpu().numpy() == 0).all()
     for a, o in zip(items, outs):
         assert_matches_oracle(a, host(o))
+
+
+@pytest.mark.parametrize("caps", [(8, 7), (5, 5)])  # 2 and 3 passes
+def test_wide_records_pass(monkeypatch, caps):
+    # 8 M cells: 8,192-cell tiles, so the records-only last pass runs with
+    # 512-thread workgroups and 4,096-cell sub-chunks (single-matrix calls)
+    _caps(monkeypatch, *caps)
+    _both(gen.large(seed=5, scale=6))

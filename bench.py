@@ -66,10 +66,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "d3959dc63ec4e642989ac9d2be12129773c9fedc3eccceb2f02208cdbd78f579",
-                       "fetch_kib": 6549164.7, "write_kib": 18367803.2},
-    "k_finish": {"sources_sha256": "d3959dc63ec4e642989ac9d2be12129773c9fedc3eccceb2f02208cdbd78f579",
-                 "fetch_kib": 27363958, "write_kib": 18591312},
+    "k_pass_scatter": {"sources_sha256": "477ebdf642c9d64b29058f6612e36c8bcbf541cad56c8a0760b6155b6d16202e",
+                       "fetch_kib": 6535209.3, "write_kib": 17863371.5},
+    "k_finish": {"sources_sha256": "477ebdf642c9d64b29058f6612e36c8bcbf541cad56c8a0760b6155b6d16202e",
+                 "fetch_kib": 27391273, "write_kib": 18591480},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

@@ -85,6 +85,33 @@ __device__ __forceinline__ void wave_add_xfer(bool active, uint32_t key, uint32_
   }
 }
 
+// Adds every active lane's cell (one cell of z bytes) to cnt[d] and byt[d] in
+// LDS with one atomic pair per run of equal digits in consecutive lanes.
+// Repeated cells (a column drawn many times in one row) otherwise send a whole
+// wave's atomics to one address, where they execute one lane at a time. The
+// lanes must hold consecutive cells, and a run's bytes stay below 2^32 (any
+// 16,384 consecutive cells do). Called by whole waves (uniform control flow).
+template <class TB>
+__device__ __forceinline__ void hist_add_runs(bool act, uint32_t d, uint32_t z, uint32_t* cnt,
+                                              TB* byt) {
+  const uint32_t lane = lane_id();
+  const uint32_t dk = act ? d : 0xFFFFFFFFu;
+  const uint32_t prev = __shfl_up(dk, 1, kWave);    // lane 0 reads its own value
+  const uint32_t next = __shfl_down(dk, 1, kWave);  // lane 63 reads its own value
+  const bool head = lane == 0 || prev != dk;
+  const bool tail = lane == kWave - 1 || next != dk;
+  const uint64_t heads = ballot(head);
+  const uint32_t zz = act ? z : 0u;
+  const uint32_t incl = wave_incl_scan_u32(zz);
+  const uint32_t excl = incl - zz;
+  const int h = 63 - (int)__clzll(heads & ((2ull << lane) - 1ull));  // this lane's run head
+  const uint32_t base = __shfl(excl, h, kWave);
+  if (act && tail) {
+    atomicAdd(&cnt[d], lane - (uint32_t)h + 1u);
+    atomicAdd(&byt[d], (TB)(incl - base));
+  }
+}
+
 __device__ __forceinline__ int ceil_log2(uint32_t x) { return x <= 1 ? 0 : 32 - __clz(x - 1); }
 
 __device__ __forceinline__ uint32_t seg_fanout(const Seg& s, uint32_t R) {
@@ -401,23 +428,25 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       mybytes = threadIdx.x == 0 ? (c_end - c_begin) * (uint64_t)fw : 0;
     else
       mybytes = threadIdx.x == 0 ? ld_full(poff, kbase + c_end, lg) - ld_full(poff, kbase + c_begin, lg) : 0;
+    // (every loop below has the same trip count on all lanes: the run
+    // aggregation works on whole waves)
     if (fw >= 0) {  // fixed-width cells: sizes are known, only the columns are read
-      for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+      for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
+        const uint64_t c = c0 + threadIdx.x;
         uint32_t key[kBatch];
 #pragma unroll
         for (int q = 0; q < kBatch; ++q)
           key[q] = (uint32_t)gm(col)[kbase + min(c + (uint64_t)q * kBlock, c_end - 1)];
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
-          if (c + (uint64_t)q * kBlock < c_end) {
-            const uint32_t d = digit_of(key[q], sg, s_lb, R);
-            atomicAdd(&s_cnt[d], 1u);
-            atomicAdd(&s_byt[d], (uint32_t)fw);
-          }
+          const bool act = c + (uint64_t)q * kBlock < c_end;
+          const uint32_t d = act ? digit_of(key[q], sg, s_lb, R) : 0u;
+          hist_add_runs(act, d, (uint32_t)fw, s_cnt, s_byt);
         }
       }
     } else
-    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+    for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
+      const uint64_t c = c0 + threadIdx.x;
       uint32_t key[kBatch], p0[kBatch], p1[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -429,16 +458,15 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        if (c + (uint64_t)q * kBlock < c_end) {
-          const uint32_t sz = p1[q] - p0[q];
-          const uint32_t d = digit_of(key[q], sg, s_lb, R);
-          atomicAdd(&s_cnt[d], 1u);
-          atomicAdd(&s_byt[d], sz);
-        }
+        const bool act = c + (uint64_t)q * kBlock < c_end;
+        const uint32_t sz = p1[q] - p0[q];
+        const uint32_t d = act ? digit_of(key[q], sg, s_lb, R) : 0u;
+        hist_add_runs(act, d, sz, s_cnt, s_byt);
       }
     }
   } else {
-    for (uint64_t c = c_begin + threadIdx.x; c < c_end; c += kStride) {
+    for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
+      const uint64_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -447,12 +475,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        if (c + (uint64_t)q * kBlock < c_end) {
-          const uint32_t d = digit_of(ks[q].x, sg, s_lb, R);
-          atomicAdd(&s_cnt[d], 1u);
-          atomicAdd(&s_byt[d], ks[q].y);
-          mybytes += ks[q].y;
-        }
+        const bool act = c + (uint64_t)q * kBlock < c_end;
+        const uint32_t d = act ? digit_of(ks[q].x, sg, s_lb, R) : 0u;
+        hist_add_runs(act, d, ks[q].y, s_cnt, s_byt);
+        if (act) mybytes += ks[q].y;
       }
     }
   }
@@ -1225,18 +1251,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
     }
     __syncthreads();
     constexpr uint32_t kStride = kBlock * kBatch;
-    for (uint32_t c = threadIdx.x; c < len; c += kStride) {
+    for (uint32_t c0 = 0; c0 < len; c0 += kStride) {  // same trip count on all lanes
+      const uint32_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) ks[q] = a.ks_in[sg.cell0 + min(c + q * kBlock, len - 1)];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
-        if (c + q * kBlock < len) {
-          uint32_t d = ks[q].x - sg.key_lo;
-          d = d < nc ? d : nc - 1;
-          atomicAdd(&s_cc[d], 1u);
-          atomicAdd((unsigned long long*)&s_cb[d], (unsigned long long)ks[q].y);
-        }
+        const bool act = c + q * kBlock < len;
+        uint32_t d = ks[q].x - sg.key_lo;
+        d = d < nc ? d : nc - 1;
+        hist_add_runs(act, d, ks[q].y, s_cc, (unsigned long long*)s_cb);
       }
     }
     __syncthreads();

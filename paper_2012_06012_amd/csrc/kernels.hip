@@ -149,8 +149,9 @@ __device__ __forceinline__ uint32_t row_of(const void* rp, int ow, uint64_t k, u
 }
 
 // Partition owning vertex v: largest p with bounds[p] <= v (0-based ranks).
-__device__ __forceinline__ uint32_t owner_of(const int32_t* lb, uint32_t R, int64_t v) {
-  uint32_t lo = 0, hi = R;
+// The partition holding index v among the bounds lb: the largest p < R with
+// lb[p] <= v, searched in [lo, hi) (lb[lo] <= v or lo = 0).
+__device__ __forceinline__ uint32_t owner_in(const int32_t* lb, uint32_t lo, uint32_t hi, int64_t v) {
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (lb[mid] <= v) lo = mid;
@@ -158,19 +159,46 @@ __device__ __forceinline__ uint32_t owner_of(const int32_t* lb, uint32_t R, int6
   }
   return lo;
 }
+__device__ __forceinline__ uint32_t owner_of(const int32_t* lb, uint32_t R, int64_t v) {
+  return owner_in(lb, 0, R, v);
+}
+
+// Coarse owner table of a partitioned pass: ot[t] = owner of index t << osh
+// for t = 0..kOwnerT, with n = lb[R] <= kOwnerT << osh. The owner of v lies
+// in [ot[v >> osh], ot[(v >> osh) + 1]]: one or two partitions unless many
+// small partitions share one table cell, instead of a search over all R.
+constexpr int kOwnerT = 1024;
+__device__ __forceinline__ int owner_shift(int64_t n) {
+  int sh = 0;
+  while (((int64_t)kOwnerT << sh) < n) ++sh;
+  return sh;
+}
+__device__ __forceinline__ void fill_owner_table(const int32_t* lb, uint32_t R, int osh,
+                                                 uint16_t* ot) {
+  for (uint32_t t = threadIdx.x; t <= (uint32_t)kOwnerT; t += blockDim.x)
+    ot[t] = (uint16_t)owner_in(lb, 0, R, (int64_t)t << osh);
+}
+__device__ __forceinline__ uint32_t owner_lut(const int32_t* lb, const uint16_t* ot, int osh,
+                                              uint32_t R, int64_t v) {
+  if (v < 0) return 0;
+  const uint64_t t = (uint64_t)v >> osh;
+  if (t >= (uint64_t)kOwnerT) return owner_in(lb, 0, R, v);  // beyond the bounds (invalid input)
+  const uint32_t hi = min((uint32_t)ot[t + 1] + 1u, R);
+  return owner_in(lb, ot[t], hi, v);
+}
 
 // Digit of a column inside a segment. Bits mode: the next `bits` bits of
 // (key - key_lo) below `shift`. Partition mode (pass 1 of a partitioned
 // matrix): the destination partition, then the top `bits` bits of the column
 // inside it. Out-of-range keys (invalid input) are clamped into the fan-out.
 __device__ __forceinline__ uint32_t digit_of(uint32_t key, const Seg& s, const int32_t* lb,
-                                             uint32_t R) {
+                                             const uint16_t* ot, int osh, uint32_t R) {
   const uint32_t m = (1u << s.bits) - 1u;
   if (s.mode == 0) {
     const uint32_t d = (key - s.key_lo) >> s.shift;
     return d > m ? m : d;
   }
-  const uint32_t p = owner_of(lb, R, (int64_t)key);
+  const uint32_t p = owner_lut(lb, ot, osh, R, (int64_t)key);
   const int64_t rel = (int64_t)key - lb[p];
   uint32_t sub = rel < 0 ? 0u : (uint32_t)(rel >> s.shift);
   sub = sub > m ? m : sub;
@@ -385,6 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   __shared__ uint32_t s_cnt[kMaxFanout];
   __shared__ uint32_t s_byt[kMaxFanout];
   __shared__ int32_t s_lb[kMaxParts + 1];
+  __shared__ uint16_t s_ot[kOwnerT + 1];
   __shared__ Seg s_seg;
   __shared__ uint32_t s_si;
   __shared__ uint64_t s_red[kNW + 1];
@@ -411,6 +440,12 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     s_byt[d] = 0;
   }
   __syncthreads();
+  int osh = 0;
+  if (sg.mode) {  // block-uniform
+    osh = owner_shift(s_lb[R]);
+    fill_owner_table(s_lb, R, osh, s_ot);
+    __syncthreads();
+  }
   const uint64_t j = tile - a.tstart[si];
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
@@ -440,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 #pragma unroll
         for (int q = 0; q < kBatch; ++q) {
           const bool act = c + (uint64_t)q * kBlock < c_end;
-          const uint32_t d = act ? digit_of(key[q], sg, s_lb, R) : 0u;
+          const uint32_t d = act ? digit_of(key[q], sg, s_lb, s_ot, osh, R) : 0u;
           hist_add_runs(act, d, (uint32_t)fw, s_cnt, s_byt);
         }
       }
@@ -460,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       for (int q = 0; q < kBatch; ++q) {
         const bool act = c + (uint64_t)q * kBlock < c_end;
         const uint32_t sz = p1[q] - p0[q];
-        const uint32_t d = act ? digit_of(key[q], sg, s_lb, R) : 0u;
+        const uint32_t d = act ? digit_of(key[q], sg, s_lb, s_ot, osh, R) : 0u;
         hist_add_runs(act, d, sz, s_cnt, s_byt);
       }
     }
@@ -476,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const bool act = c + (uint64_t)q * kBlock < c_end;
-        const uint32_t d = act ? digit_of(ks[q].x, sg, s_lb, R) : 0u;
+        const uint32_t d = act ? digit_of(ks[q].x, sg, s_lb, s_ot, osh, R) : 0u;
         hist_add_runs(act, d, ks[q].y, s_cnt, s_byt);
         if (act) mybytes += ks[q].y;
       }
@@ -926,6 +961,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
   __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
   __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
+  __shared__ uint16_t s_ot[kPass0 ? kOwnerT + 1 : 1];   // their coarse owner table
   __shared__ Seg s_seg;
   __shared__ uint32_t s_si, s_extra;
   __shared__ uint32_t s_red[kNW + 1];
@@ -981,6 +1017,14 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
     rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
   }
   __syncthreads();
+  int osh = 0;
+  if constexpr (kPass0) {
+    if (sg.mode) {  // block-uniform
+      osh = owner_shift(s_lb[R]);
+      fill_owner_table(s_lb, R, osh, s_ot);
+      __syncthreads();
+    }
+  }
   uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 
@@ -1035,7 +1079,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
-      dg[r] = i < n ? digit_of(key[r], sg, s_lb, R) : 0u;
+      dg[r] = i < n ? digit_of(key[r], sg, s_lb, s_ot, osh, R) : 0u;
     }
     // The next sub-chunk's loads go out once this one's registers have been
     // read (the wait counter is in order, so a use of the current loads after
@@ -1114,7 +1158,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
         if (xfer_per_cell) {  // the sub-chunk spans source partitions (uniform)
           uint32_t key = 0;
           if (i < n) {
-            const uint32_t sp = owner_of(s_lb, R, (int64_t)L.row[i]);
+            const uint32_t sp = owner_lut(s_lb, s_ot, osh, R, (int64_t)L.row[i]);
             key = sp * R + (L.dig[i] >> sg.bits);
           }
           wave_add_xfer(i < n, key, pz[q], (uint64_t*)it->xfer_cells, (uint64_t*)it->xfer_bytes);

@@ -1212,12 +1212,16 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
 __global__ __launch_bounds__(kBlock) void k_view_keys(ViewArgs a) {
   __shared__ uint32_t incl[kSub];
   __shared__ int32_t s_lb[kMaxParts + 1];
+  __shared__ uint16_t s_ot[kOwnerT + 1];
   __shared__ uint32_t s_extra;
   __shared__ uint32_t s_red[kNW + 1];
   if (aborted(a.abort_flag)) return;
   const ItemDev& it = a.items[0];
   const uint32_t R = (uint32_t)a.n_parts;
   for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(a.bounds)[i];
+  __syncthreads();
+  const int osh = owner_shift(s_lb[R]);
+  fill_owner_table(s_lb, R, osh, s_ot);
   __syncthreads();
   const uint64_t k0 = (uint64_t)blockIdx.x * kSub;
   if (k0 >= a.nnz) return;
@@ -1233,15 +1237,15 @@ __global__ __launch_bounds__(kBlock) void k_view_keys(ViewArgs a) {
     const int64_t j = gm(a.col)[k];
     uint64_t key, val;
     if (!a.column_view) {
-      key = a.op == 0 ? (uint64_t)owner_of(s_lb, R, (int64_t)v) * (uint64_t)a.n_cols + (uint64_t)j
-                      : (uint64_t)owner_of(s_lb, R, j) * (uint64_t)a.n_rows + v;
+      key = a.op == 0 ? (uint64_t)owner_lut(s_lb, s_ot, osh, R, (int64_t)v) * (uint64_t)a.n_cols + (uint64_t)j
+                      : (uint64_t)owner_lut(s_lb, s_ot, osh, R, j) * (uint64_t)a.n_rows + v;
       val = a.op == 0 ? v : (uint64_t)j;
       if (a.validate && (j < 0 || j >= a.n_cols)) bad = true;
     } else {
       const uint64_t s = v / (uint64_t)a.n_rows, i_row = v - s * (uint64_t)a.n_rows;
       key = a.op == 0 ? (uint64_t)j : i_row;
       val = a.op == 0 ? i_row : (uint64_t)j;
-      if (a.validate && (j < 0 || j >= a.n_cols || owner_of(s_lb, R, j) != s)) bad = true;
+      if (a.validate && (j < 0 || j >= a.n_cols || owner_lut(s_lb, s_ot, osh, R, j) != s)) bad = true;
     }
     gm(a.keys)[k] = (uint32_t)key;
     gm(a.vals)[k] = (uint32_t)val;

@@ -39,9 +39,10 @@
  * MGT_VALIDATE, invalid data is undefined behaviour. On success *d_status is
  * MGT_OK. d_status may be NULL.
  *
- * Thread safety: a plan is immutable after creation and may be used from
- * several threads; concurrent calls need distinct workspaces (and, for the
- * batch entry point, distinct plans, since a plan owns its staging buffer).
+ * Thread safety: a plan's parameters are fixed at creation, and calls from
+ * several threads may share a plan (the library serialises the host part of
+ * calls on one plan: the descriptor upload through the plan's pinned staging
+ * buffer). Calls whose device work may overlap need distinct workspaces.
  */
 #ifndef MGT_H
 #define MGT_H

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -324,6 +325,9 @@ struct mgt_plan_s {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   Timing timing;
+  // Serialises the host part of calls on this plan (staging buffer, upload
+  // event, stage-timing events): calls from several threads may share it.
+  std::mutex mu;
   // view-operation plans (mgt_view_plan): the operation, the input view, and
   // the descriptor the passes see (virtual rows, sort keys as columns)
   int32_t view_op = -1, column_view = 0;
@@ -649,7 +653,11 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   if (!partitioned) it.bounds = nullptr;
   Layout y = make_layout(items);
   if (ws_bytes < y.bytes) return MGT_ENOMEM;
-  if (graph) return record_graph(p, items, y, ws, d_status, graph);
+  if (graph) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    return record_graph(p, items, y, ws, d_status, graph);
+  }
+  std::lock_guard<std::mutex> lock(p->mu);
   p->timing.used = 0;
   return run(p, items, y, ws, d_status, s);
 }
@@ -833,6 +841,7 @@ int mgt_view_transform(mgt_plan_t p, const void* row_ptr, const int32_t* col,
   it.dev.col = (const int32_t*)(W + y.o_vkeys);  // the passes sort by the keys ...
   it.dev.vval = (const uint32_t*)(W + y.o_vvals);  // ... and carry the values
   ViewCall vc{col, p->bounds.data(), p->desc.n_rows, p->desc.n_cols, p->view_op, p->column_view};
+  std::lock_guard<std::mutex> lock(p->mu);
   p->timing.used = 0;
   return run(p, items, y, workspace, d_status, stream, &vc);
 }
@@ -922,6 +931,7 @@ int mgt_batch_submit(mgt_plan_t plan, const mgt_item* items, int32_t n_items, vo
   if (!workspace || ((uintptr_t)workspace & 255u)) return MGT_EINVAL;
   Layout y = make_layout(hi);
   if (workspace_bytes < y.bytes) return MGT_ENOMEM;
+  std::lock_guard<std::mutex> lock(plan->mu);
   plan->timing.used = 0;
   st = run(plan, hi, y, workspace, d_status, stream);
   if (st != MGT_OK) return st;
@@ -932,6 +942,7 @@ int mgt_batch_submit(mgt_plan_t plan, const mgt_item* items, int32_t n_items, vo
 int mgt_plan_stage_times(mgt_plan_t plan, float* ms, const char** names, int32_t capacity,
                          int32_t* count) {
   if (!plan || !count) return MGT_EINVAL;
+  std::lock_guard<std::mutex> lock(plan->mu);
   Timing& t = plan->timing;
   const int n = t.used > 1 ? t.used - 1 : 0;
   *count = n;

@@ -5,8 +5,9 @@ import this package. It wraps ``oracle.c`` (a plain single-threaded
 counting-sort transpose written from the paper's definitions) and adds two
 pure-Python/numpy cross-checks: ``brute`` (sort every cell by its transposed
 key) and ``staged`` (a rank-by-rank simulation of the paper's staged
-algorithm), and ``views`` (the Section 3 LocalTranspose and ViewSwap on their
-own). The GPU library shares no code with anything here.
+algorithm), ``views`` (the Section 3 LocalTranspose and ViewSwap on their
+own) and ``values`` (XCSR value lists against repeated cells, Section 2). The
+GPU library shares no code with anything here.
 """
 from __future__ import annotations
 

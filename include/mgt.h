@@ -255,6 +255,57 @@ int mgt_batch_submit(mgt_plan_t batch_plan, const mgt_item* items, int32_t n_ite
                      void* workspace, size_t workspace_bytes, int32_t* d_status,
                      hipStream_t stream, hipEvent_t done);
 
+/* ------------------------------------------------------------------ value lists */
+
+/*
+ * XCSR value lists (Section 2). The paper keeps one cell per (row, column)
+ * pair whose value is a list of values, serialised as all values back to back
+ * plus a count of values per cell (its cell_counts argument); a multigraph can
+ * keep every edge as a cell of its own instead, so a pair with N edges is N
+ * repeated cells. Both are CSRs over the same payload array here: the payload
+ * bytes keep their order, so these calls neither read nor write them and the
+ * caller keeps using its payload buffer. Every call is asynchronous on
+ * `stream`; offset_width (4 or 8) is the width of every row-offset and
+ * payload-offset array, in and out. Device pointers unless stated.
+ *
+ * mgt_coalesce: every run of consecutive cells of one row with the same
+ *   column becomes one cell whose payload is the run's payloads in order.
+ *   o_counts[j] (may be NULL) receives the run's length: the value count when
+ *   every repeated cell holds one value. Rows sorted by column (every
+ *   transpose output) give one cell per distinct (row, column) pair. Output
+ *   capacity: o_row_ptr[n_rows + 1], o_col[nnz], o_payload_off[nnz + 1],
+ *   o_counts[nnz]; the number m of output cells is written to *d_m (device
+ *   int64; may be NULL) and entries past m are left alone. workspace: at least
+ *   mgt_value_lists_workspace(nnz) bytes, 256-byte aligned.
+ * mgt_expand: every cell whose payload is a list of value_bytes-wide values
+ *   becomes one cell per value with the cell's row and column, in order:
+ *   payload_bytes / value_bytes output cells (payload_bytes must be a
+ *   multiple of value_bytes, else MGT_EINVAL). Outputs: o_row_ptr[n_rows + 1],
+ *   o_col[payload_bytes / value_bytes], o_payload_off (may be NULL) receives
+ *   q * value_bytes. If a payload offset is not a multiple of value_bytes,
+ *   *d_status (may be NULL) is MGT_ERANGE and the outputs are undefined;
+ *   otherwise MGT_OK.
+ * mgt_counts_to_offsets: payload_off[k] = value_bytes * (counts[0] + ... +
+ *   counts[k-1]) for k = 0..nnz, from the paper's per-cell value counts.
+ *   Same workspace as mgt_coalesce.
+ *
+ * Sizes: nnz and the output cell count below 2^32, n_rows below 2^31, else
+ * MGT_EUNSUPPORTED. Rows and offsets that break the CSR invariants give
+ * undefined outputs but no out-of-bounds access.
+ */
+int mgt_value_lists_workspace(int64_t nnz, size_t* workspace_bytes);
+int mgt_coalesce(int64_t n_rows, int64_t nnz, int32_t offset_width, const void* row_ptr,
+                 const int32_t* col, const void* payload_off, void* o_row_ptr, int32_t* o_col,
+                 void* o_payload_off, uint32_t* o_counts, int64_t* d_m, void* workspace,
+                 size_t workspace_bytes, hipStream_t stream);
+int mgt_expand(int64_t n_rows, int64_t nnz, int64_t payload_bytes, int32_t offset_width,
+               int32_t value_bytes, const void* row_ptr, const int32_t* col,
+               const void* payload_off, void* o_row_ptr, int32_t* o_col, void* o_payload_off,
+               int32_t* d_status, hipStream_t stream);
+int mgt_counts_to_offsets(int64_t nnz, const uint32_t* counts, int32_t value_bytes,
+                          int32_t offset_width, void* payload_off, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------ graphs */
 
 /*

@@ -79,17 +79,24 @@ _lib.mgt_view_transform.argtypes = [_vp] * 10 + [_vp, _sz, _vp, _vp]
 _lib.mgt_graph_create.argtypes = [_vp, _i32] + [_vp] * 16 + [_sz, _vp, ctypes.POINTER(_vp)]
 _lib.mgt_graph_launch.argtypes = [_vp, _vp]
 _lib.mgt_graph_destroy.argtypes = [_vp]
+_i64 = ctypes.c_int64
+_lib.mgt_value_lists_workspace.argtypes = [_i64, ctypes.POINTER(_sz)]
+_lib.mgt_coalesce.argtypes = [_i64, _i64, _i32] + [_vp] * 9 + [_sz, _vp]
+_lib.mgt_expand.argtypes = [_i64, _i64, _i64, _i32, _i32] + [_vp] * 7 + [_vp]
+_lib.mgt_counts_to_offsets.argtypes = [_i64, _vp, _i32, _i32, _vp, _vp, _sz, _vp]
 _lib.mgt_version.restype = ctypes.c_char_p
 for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
            "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
-           "mgt_graph_destroy"):
+           "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce", "mgt_expand",
+           "mgt_counts_to_offsets"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
             "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
             "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
-            "mgt_graph_launch", "mgt_graph_destroy")
+            "mgt_graph_launch", "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce",
+            "mgt_expand", "mgt_counts_to_offsets")
 
 
 def version() -> str:
@@ -228,6 +235,37 @@ def mgt_graph_create(plan: Plan, partitioned: bool, row_ptr, col, payload_off, p
         workspace.numel() * workspace.element_size(), _ptr(d_status), ctypes.byref(h)),
         "mgt_graph_create")
     return Graph(h.value, args)
+
+
+def mgt_value_lists_workspace(nnz: int) -> int:
+    ws = _sz()
+    _check(_lib.mgt_value_lists_workspace(nnz, ctypes.byref(ws)), "mgt_value_lists_workspace")
+    return ws.value
+
+
+def mgt_coalesce(n_rows: int, nnz: int, offset_width: int, row_ptr, col, payload_off, o_row_ptr,
+                 o_col, o_payload_off, o_counts, d_m, workspace, stream=None) -> None:
+    _check(_lib.mgt_coalesce(n_rows, nnz, offset_width, _ptr(row_ptr), _ptr(col),
+                             _ptr(payload_off), _ptr(o_row_ptr), _ptr(o_col),
+                             _ptr(o_payload_off), _ptr(o_counts), _ptr(d_m), _ptr(workspace),
+                             workspace.numel() * workspace.element_size(), _stream(stream)),
+           "mgt_coalesce")
+
+
+def mgt_expand(n_rows: int, nnz: int, payload_bytes: int, offset_width: int, value_bytes: int,
+               row_ptr, col, payload_off, o_row_ptr, o_col, o_payload_off, d_status=None,
+               stream=None) -> None:
+    _check(_lib.mgt_expand(n_rows, nnz, payload_bytes, offset_width, value_bytes, _ptr(row_ptr),
+                           _ptr(col), _ptr(payload_off), _ptr(o_row_ptr), _ptr(o_col),
+                           _ptr(o_payload_off), _ptr(d_status), _stream(stream)), "mgt_expand")
+
+
+def mgt_counts_to_offsets(nnz: int, counts, value_bytes: int, offset_width: int, payload_off,
+                          workspace, stream=None) -> None:
+    _check(_lib.mgt_counts_to_offsets(nnz, _ptr(counts), value_bytes, offset_width,
+                                      _ptr(payload_off), _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(),
+                                      _stream(stream)), "mgt_counts_to_offsets")
 
 
 def mgt_view_plan(n_rows: int, n_cols: int, nnz: int, payload_bytes: int, offset_width: int,
@@ -396,6 +434,44 @@ def transpose_graph(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, p
                          out.get("part_cell_off"), out.get("part_byte_off"), out.get("sdispls"),
                          out.get("rdispls"), workspace, status)
     return g, out, status
+
+
+def coalesce(a: DeviceCsr, stream=None):
+    """Runs of repeated (row, column) cells merged into XCSR value-list cells.
+
+    Returns (outputs dict with row_ptr, col, payload_off, counts trimmed to the
+    m output cells, m). The payload tensor of `a` is the payload of the result.
+    Synchronises to read m."""
+    dev = a.col.device
+    odt = torch.int32 if a.offset_width == 4 else torch.int64
+    if a.payload_off is None:
+        raise ValueError("coalesce needs the payload offsets")
+    o_rp = torch.empty(a.n_rows + 1, dtype=odt, device=dev)
+    o_col = torch.empty(a.nnz, dtype=torch.int32, device=dev)
+    o_poff = torch.empty(a.nnz + 1, dtype=odt, device=dev)
+    o_cnt = torch.empty(a.nnz, dtype=torch.int32, device=dev)
+    d_m = torch.zeros(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(max(mgt_value_lists_workspace(a.nnz), 256), dtype=torch.uint8, device=dev)
+    mgt_coalesce(a.n_rows, a.nnz, a.offset_width, a.row_ptr, a.col, a.payload_off, o_rp, o_col,
+                 o_poff, o_cnt, d_m, ws, stream)
+    m = int(d_m.cpu()[0])
+    return dict(row_ptr=o_rp, col=o_col[:m], payload_off=o_poff[:m + 1], counts=o_cnt[:m]), m
+
+
+def expand(a: DeviceCsr, value_bytes: int, payload_off: bool = True, stream=None):
+    """One cell per value_bytes-wide value. Returns (outputs dict, status tensor)."""
+    dev = a.col.device
+    odt = torch.int32 if a.offset_width == 4 else torch.int64
+    if a.payload_off is None:
+        raise ValueError("expand needs the payload offsets")
+    nv = a.payload_bytes // value_bytes
+    out = dict(row_ptr=torch.empty(a.n_rows + 1, dtype=odt, device=dev),
+               col=torch.empty(nv, dtype=torch.int32, device=dev),
+               payload_off=torch.empty(nv + 1, dtype=odt, device=dev) if payload_off else None)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    mgt_expand(a.n_rows, a.nnz, a.payload_bytes, a.offset_width, value_bytes, a.row_ptr, a.col,
+               a.payload_off, out["row_ptr"], out["col"], out["payload_off"], status, stream)
+    return out, status
 
 
 def batch_entries(mats: Sequence[DeviceCsr], outs: Sequence[dict], perm: bool = False,

@@ -233,3 +233,33 @@ def test_batch_plan_limits_and_exact_workspace():
     items5 = mgt.make_items(entries * 3)
     with pytest.raises(mgt.MgtError):
         mgt.mgt_batch_workspace(bp, items5)
+
+
+def test_value_list_calls_reject_before_launch():
+    mgt = _lib()
+    lib = ctypes.CDLL(mgt.LIB_PATH)
+    assert mgt.mgt_value_lists_workspace(0) >= 256
+    assert mgt.mgt_value_lists_workspace(1 << 20) > mgt.mgt_value_lists_workspace(1 << 10)
+    with pytest.raises(mgt.MgtError):
+        mgt.mgt_value_lists_workspace(1 << 32)
+    v, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.mgt_coalesce.argtypes = [i64, i64, i32] + [v] * 9 + [sz, v]
+    lib.mgt_expand.argtypes = [i64, i64, i64, i32, i32] + [v] * 8
+    lib.mgt_counts_to_offsets.argtypes = [i64, v, i32, i32, v, v, sz, v]
+    fake = ctypes.c_void_p(4096)
+    ws = mgt.mgt_value_lists_workspace(100)
+    # bad offset width, missing outputs, misaligned or short workspace
+    assert lib.mgt_coalesce(10, 100, 2, fake, fake, fake, fake, fake, fake, None, None, fake, ws,
+                            None) == -1
+    assert lib.mgt_coalesce(10, 100, 8, fake, fake, fake, fake, None, fake, None, None, fake, ws,
+                            None) == -1
+    assert lib.mgt_coalesce(10, 100, 8, fake, fake, fake, fake, fake, fake, None, None,
+                            ctypes.c_void_p(4097), ws, None) == -1
+    assert lib.mgt_coalesce(10, 100, 8, fake, fake, fake, fake, fake, fake, None, None, fake, 16,
+                            None) == -3
+    # payload not a whole number of values; zero value width; too many values
+    assert lib.mgt_expand(10, 100, 401, 8, 4, fake, fake, fake, fake, fake, None, None, None) == -1
+    assert lib.mgt_expand(10, 100, 400, 8, 0, fake, fake, fake, fake, fake, None, None, None) == -1
+    assert lib.mgt_expand(10, 100, 1 << 40, 8, 4, fake, fake, fake, fake, fake, None, None,
+                          None) == -5
+    assert lib.mgt_counts_to_offsets(100, None, 4, 8, fake, fake, ws, None) == -1

@@ -233,17 +233,18 @@ def bench_serve(args):
     from paper_2012_06012_amd.serve import Request, Server
     dev = torch.device("cuda:0")
     t0 = time.time()
-    pool_n = 32
+    pool_n = args.serve_pool
     host = []
     for i in range(pool_n):
-        cells, n, deg, width, r = gen.served_request_params(args.seed, i, 1e4, 1e7)
+        cells, n, deg, width, r = gen.served_request_params(args.seed, i, 1e4, args.serve_c_hi)
         host.append(gen.generate(n, n, seed=(args.seed << 24) + i + 11, deg_law=gen.DEG_POISSON,
                                  deg_mean=float(deg), pay_law=gen.PAY_BYTES, w_lo=width,
                                  w_hi=width, offset_width=8, bounds=gen.equal_bounds(n, min(r, n))))
     pool = [_device(a, dev) for a in host]
-    log(f"[serve] pool of {pool_n} inputs, {sum(a.nnz for a in host)} cells, "
-        f"{time.time() - t0:.1f}s")
-    n_req = args.items
+    pool_cells = sum(a.nnz for a in host)
+    del host
+    log(f"[serve] pool of {pool_n} inputs, {pool_cells} cells, {time.time() - t0:.1f}s")
+    n_req = args.serve_requests
 
     def make(rate):
         arr = gen.poisson_arrivals(n_req, rate, args.seed + 3)
@@ -251,28 +252,35 @@ def bench_serve(args):
                 for i, t in enumerate(arr)]
 
     budget = 200 << 30
+
+    def release(r):  # a served request's outputs go back to the caller at completion
+        r.outputs = None
     # capacity of the plain path: back-to-back, no arrivals gaps
-    plain = Server(serve.PlainExecutor(), budget, max_batch=1, n_slots=1)
+    plain = Server(serve.PlainExecutor(), budget, max_batch=1, n_slots=1, on_done=release)
+    cap_n = 2 * pool_n  # every pool input twice, back to back
     st = plain.run([Request(rid=i, mat=pool[i % pool_n], arrival=0.0,
-                            partitioned=pool[i % pool_n].n_parts > 1) for i in range(64)])
-    mu = 64 / st.last_done
+                            partitioned=pool[i % pool_n].n_parts > 1) for i in range(cap_n)])
+    mu = cap_n / st.last_done
     log(f"[serve] plain capacity {mu:.1f} req/s")
     out = {}
-    bex = serve.GpuExecutor(n_slots=2, max_items=64)
+    # at most 2^26 cells (a few ms of device work) per batch: large requests
+    # run alone instead of holding a batch of small ones back
+    bex = serve.GpuExecutor(n_slots=2, max_items=64, batch_cells=1 << 26)
     pex = serve.PlainExecutor()
-    warm = 64  # warm-up requests per rate: device allocations are made and cached there
+    warm = args.serve_warmup  # per rate: device allocations are made and cached there
     for frac in (0.5, 0.7, 0.9, 1.2):
         rate = frac * mu
-        Server(bex, budget, max_batch=32, n_slots=2).run(make(rate)[:warm])
-        sb = Server(bex, budget, max_batch=32, n_slots=2).run(make(rate))
-        Server(pex, budget, max_batch=1, n_slots=1).run(make(rate)[:warm])
-        sp = Server(pex, budget, max_batch=1, n_slots=1).run(make(rate))
+        Server(bex, budget, max_batch=32, n_slots=2, on_done=release).run(make(rate)[:warm])
+        sb = Server(bex, budget, max_batch=32, n_slots=2, on_done=release).run(make(rate))
+        Server(pex, budget, max_batch=1, n_slots=1, on_done=release).run(make(rate)[:warm])
+        sp = Server(pex, budget, max_batch=1, n_slots=1, on_done=release).run(make(rate))
         out[f"{frac}mu"] = {"batched": sb.summary(), "plain": sp.summary()}
         log(f"[serve] rate {rate:.1f}/s: batched {sb.summary()} plain {sp.summary()}")
     res = {"metric": "served p50/p99 latency and sustained cells/s, batched vs plain",
            "mode": "serve", "requests": n_req, "warmup_requests": warm,
            "plain_capacity_req_s": mu, "results": out,
-           "config": {"workload": "requests of log-uniform 1e4-1e7 cells, widths U{0..32}, "
+           "config": {"workload": f"requests of log-uniform 1e4-{args.serve_c_hi:.0e} cells from a "
+                                  f"pool of {pool_n} device-resident inputs, widths U{{0..32}}, "
                                   "R U{1..64}, Poisson arrivals", "budget_bytes": budget}}
     print(json.dumps(res), flush=True)
 
@@ -443,7 +451,11 @@ def main():
                     help="plain: the headline line; batch: many matrices in one mgt_batch_submit "
                          "vs per-matrix launches; serve: the continuous-batching request loop vs "
                          "per-request plain launches")
-    ap.add_argument("--items", type=int, default=512, help="batch / serve: matrices or requests")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="serve: requests per rate")
+    ap.add_argument("--serve-warmup", type=int, default=100, help="serve: warm-up requests per rate")
+    ap.add_argument("--serve-pool", type=int, default=128, help="serve: distinct resident inputs")
+    ap.add_argument("--serve-c-hi", type=float, default=1e8,
+                    help="serve: largest request size (cells) of the log-uniform range")
     ap.add_argument("--batch-items", type=int, default=4096, help="batch: matrices")
     ap.add_argument("--batch-budget", type=float, default=200e9,
                     help="batch: estimated device bytes per wave of matrices")

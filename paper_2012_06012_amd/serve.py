@@ -85,7 +85,13 @@ class Stats:
 class Server:
     def __init__(self, executor, budget_bytes: int, max_batch: int = 64, n_slots: int = 2,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, max_attempts: int = 3):
+                 sleep: Callable[[float], None] = time.sleep, max_attempts: int = 3,
+                 on_done: Optional[Callable[[Request], None]] = None):
+        # on_done(request) runs when a request completes (or fails): where its
+        # outputs are handed over. The budget counts a request's footprint
+        # until then only, so a caller that keeps every output must size the
+        # budget for that.
+        self.on_done = on_done
         self.ex = executor
         self.budget = budget_bytes
         self.max_batch = max_batch
@@ -134,7 +140,17 @@ class Server:
             # submit to free slots
             while free_slots and ready:
                 slot = free_slots.pop(0)
-                batch, ready = ready[:self.max_batch], ready[self.max_batch:]
+                # up to max_batch requests, and within the executor's cells per
+                # batch (a request larger than that goes alone)
+                cap = getattr(self.ex, "max_batch_cells", None)
+                take, cells = 0, 0
+                while take < len(ready) and take < self.max_batch:
+                    c = ready[take].nnz
+                    if take and cap is not None and cells + c > cap:
+                        break
+                    cells += c
+                    take += 1
+                batch, ready = ready[:take], ready[take:]
                 for r in batch:
                     r.submit_t = now
                     r.attempts += 1
@@ -159,6 +175,8 @@ class Server:
                     r.status = s
                     r.done_t = done_t
                     used -= r.footprint
+                    if self.on_done is not None:
+                        self.on_done(r)
                     if s == OK:
                         st.completed += 1
                         st.cells += r.nnz
@@ -188,7 +206,7 @@ class GpuExecutor:
 
     def __init__(self, n_slots: int, offset_width: int = 8, perm: bool = False,
                  validate: bool = False, max_items: int = 256, max_cells: int = 1 << 31,
-                 max_cols: int = 1 << 30):
+                 max_cols: int = 1 << 30, batch_cells: Optional[int] = None):
         import torch
         from . import mgt
         self.torch = torch
@@ -199,6 +217,9 @@ class GpuExecutor:
         self.plans = [mgt.mgt_batch_plan(max_items, max_cells, max_cols, max_cols, 1 << 20,
                                          max_cells, max_cols, offset_width, self.flags)
                       for _ in range(n_slots)]
+        # the server forms batches within this many cells (a larger request
+        # still runs, alone); the plans take up to max_cells
+        self.max_batch_cells = min(batch_cells or max_cells, max_cells)
         self.ws = [None] * n_slots
 
     def footprint(self, r: Request) -> int:

@@ -114,3 +114,13 @@ def test_failure_isolation_resubmits_cancelled():
 def test_stats_percentiles():
     s = Stats(latencies=[float(i) for i in range(1, 101)])
     assert s.percentile(50) == 50.0 and s.percentile(99) == 99.0
+
+
+def test_batches_respect_the_executors_cell_cap():
+    clock = Clock()
+    ex = FakeExecutor(clock)
+    ex.max_batch_cells = 250
+    reqs = _reqs([100, 100, 100, 400, 50, 50], [0.0] * 6)
+    st = Server(ex, 10 ** 9, max_batch=8, n_slots=1, clock=clock.now, sleep=clock.sleep).run(reqs)
+    assert st.completed == 6
+    assert [rids for _, _, _, rids in ex.log] == [[0, 1], [2], [3], [4, 5]]

@@ -154,7 +154,7 @@ def bench_batch(args):
     if cur:
         waves.append(cur)
     log(f"[batch] {n_items} matrices in {len(waves)} waves (budget {args.batch_budget:.3g} B)")
-    tot_cells, ms_b_tot, ms_p_tot, same_all = 0, 0.0, 0.0, True
+    tot_cells, ms_b_tot, ms_g_tot, ms_p_tot, same_all = 0, 0.0, 0.0, 0.0, True
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for wi, idx in enumerate(waves):
         t0 = time.time()
@@ -172,6 +172,18 @@ def bench_batch(args):
         torch.cuda.synchronize()
         ms_b = ev0.elapsed_time(ev1) / args.steps
         ok_status = bool((status.cpu().numpy() == 0).all())
+        # the same submit recorded once as a graph and replayed (same outputs)
+        g, _, gst, _, _ = mgt.batch_graph(mats, plan=plan, workspace=ws, outs=outs)
+        g.launch()
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.steps):
+            g.launch()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_g = ev0.elapsed_time(ev1) / args.steps
+        ok_status = ok_status and bool((gst.cpu().numpy() == 0).all())
+        g.close()
         # one mgt_transpose per matrix into one scratch output set
         plans = [mgt.plan_for(a) for a in mats]
         ws1 = torch.empty(max(max(p.workspace_bytes for p in plans), 256), dtype=torch.uint8,
@@ -206,16 +218,18 @@ def bench_batch(args):
             same = same and all(torch.equal(o[k], ob[k]) for k in
                                 ("t_row_ptr", "t_col", "t_payload_off", "t_payload"))
         torch.cuda.synchronize()
-        log(f"[batch] wave {wi}: batched {ms_b:.1f} ms, one by one {ms_p:.1f} ms, bit-exact {same}")
+        log(f"[batch] wave {wi}: batched {ms_b:.1f} ms (graph replay {ms_g:.1f} ms), one by one "
+            f"{ms_p:.1f} ms, bit-exact {same}")
         tot_cells += cells
         ms_b_tot += ms_b
+        ms_g_tot += ms_g
         ms_p_tot += ms_p
         same_all = same_all and same
-        del mats, outs, status, plan, ws, plans, ws1, flat, views
+        del mats, outs, status, plan, ws, plans, ws1, flat, views, g, gst
         torch.cuda.empty_cache()
     res = {"metric": "cells/s, batched vs per-matrix plain launches", "mode": "batch",
            "matrices": n_items, "waves": len(waves), "cells": tot_cells,
-           "ms_batched": ms_b_tot, "ms_per_matrix_plain": ms_p_tot,
+           "ms_batched": ms_b_tot, "ms_batched_graph": ms_g_tot, "ms_per_matrix_plain": ms_p_tot,
            "cells_per_s_batched": tot_cells / (ms_b_tot * 1e-3),
            "cells_per_s_plain": tot_cells / (ms_p_tot * 1e-3), "speedup": ms_p_tot / ms_b_tot,
            "bit_exact_batched_vs_plain": bool(same_all),

@@ -331,6 +331,13 @@ int mgt_graph_create(mgt_plan_t plan, int32_t partitioned, const void* row_ptr,
                      int64_t* part_cell_off, int64_t* part_byte_off, int64_t* sdispls,
                      int64_t* rdispls, void* workspace, size_t workspace_bytes,
                      int32_t* d_status, mgt_graph_t* out);
+/* The same for one mgt_batch_submit call (a batch of n_items >= 1 items with
+ * these exact buffers): every replay transposes all items with the batch's
+ * fixed launch sequence. Arguments and errors as for mgt_batch_submit; plans
+ * with MGT_DEBUG_TIMING give MGT_EINVAL. */
+int mgt_batch_graph_create(mgt_plan_t batch_plan, const mgt_item* items, int32_t n_items,
+                           void* workspace, size_t workspace_bytes, int32_t* d_status,
+                           mgt_graph_t* out);
 int mgt_graph_launch(mgt_graph_t graph, hipStream_t stream);
 int mgt_graph_destroy(mgt_graph_t graph);
 

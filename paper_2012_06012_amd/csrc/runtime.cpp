@@ -939,6 +939,33 @@ int mgt_batch_submit(mgt_plan_t plan, const mgt_item* items, int32_t n_items, vo
   return MGT_OK;
 }
 
+int mgt_batch_graph_create(mgt_plan_t plan, const mgt_item* items, int32_t n_items,
+                           void* workspace, size_t workspace_bytes, int32_t* d_status,
+                           mgt_graph_t* out) {
+  if (!out) return MGT_EINVAL;
+  if (plan && (plan->flags & MGT_DEBUG_TIMING)) return MGT_EINVAL;
+  std::vector<HostItem> hi;
+  int st = batch_items(plan, items, n_items, hi);
+  if (st != MGT_OK) return st;
+  if (n_items == 0) return MGT_EINVAL;  // nothing to record
+  if (!workspace || ((uintptr_t)workspace & 255u)) return MGT_EINVAL;
+  Layout y = make_layout(hi);
+  if (workspace_bytes < y.bytes) return MGT_ENOMEM;
+  mgt_graph_s* g = new (std::nothrow) mgt_graph_s();
+  if (!g) return MGT_ENOMEM;
+  {
+    std::lock_guard<std::mutex> lock(plan->mu);
+    st = record_graph(plan, hi, y, workspace, d_status, g);
+  }
+  if (st == MGT_OK && !g->exec) st = MGT_EINVAL;
+  if (st != MGT_OK) {
+    mgt_graph_destroy(g);
+    return st;
+  }
+  *out = g;
+  return MGT_OK;
+}
+
 int mgt_plan_stage_times(mgt_plan_t plan, float* ms, const char** names, int32_t capacity,
                          int32_t* count) {
   if (!plan || !count) return MGT_EINVAL;

@@ -78,6 +78,8 @@ _lib.mgt_view_plan.argtypes = [ctypes.POINTER(Desc), _i32, _i32, ctypes.POINTER(
 _lib.mgt_view_transform.argtypes = [_vp] * 10 + [_vp, _sz, _vp, _vp]
 _lib.mgt_graph_create.argtypes = [_vp, _i32] + [_vp] * 16 + [_sz, _vp, ctypes.POINTER(_vp)]
 _lib.mgt_graph_launch.argtypes = [_vp, _vp]
+_lib.mgt_batch_graph_create.argtypes = [_vp, ctypes.POINTER(Item), _i32, _vp, _sz, _vp,
+                                        ctypes.POINTER(_vp)]
 _lib.mgt_graph_destroy.argtypes = [_vp]
 _i64 = ctypes.c_int64
 _lib.mgt_value_lists_workspace.argtypes = [_i64, ctypes.POINTER(_sz)]
@@ -89,14 +91,14 @@ for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_parti
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
            "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
            "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce", "mgt_expand",
-           "mgt_counts_to_offsets"):
+           "mgt_counts_to_offsets", "mgt_batch_graph_create"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
             "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
             "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
             "mgt_graph_launch", "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce",
-            "mgt_expand", "mgt_counts_to_offsets")
+            "mgt_expand", "mgt_counts_to_offsets", "mgt_batch_graph_create")
 
 
 def version() -> str:
@@ -214,6 +216,7 @@ class Graph:
         if self.handle:
             _lib.mgt_graph_destroy(self.handle)
             self.handle = None
+        self._keep = ()
 
     def __del__(self):
         try:
@@ -266,6 +269,15 @@ def mgt_counts_to_offsets(nnz: int, counts, value_bytes: int, offset_width: int,
                                       _ptr(payload_off), _ptr(workspace),
                                       workspace.numel() * workspace.element_size(),
                                       _stream(stream)), "mgt_counts_to_offsets")
+
+
+def mgt_batch_graph_create(plan: Plan, items: ctypes.Array, workspace, d_status=None,
+                           keep: tuple = ()) -> Graph:
+    h = _vp()
+    _check(_lib.mgt_batch_graph_create(plan.handle, items, len(items), _ptr(workspace),
+                                       workspace.numel() * workspace.element_size(),
+                                       _ptr(d_status), ctypes.byref(h)), "mgt_batch_graph_create")
+    return Graph(h.value, (items, workspace, d_status) + tuple(keep))
 
 
 def mgt_view_plan(n_rows: int, n_cols: int, nnz: int, payload_bytes: int, offset_width: int,
@@ -516,6 +528,31 @@ def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm
     mgt_batch_submit(plan, items, workspace, status, stream, done_event)
     del keep
     return outs, status, plan, workspace
+
+
+def batch_graph(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm: bool = False,
+                validate: bool = False, outs=None, workspace=None):
+    """Records one batch transpose of `mats` into fixed outputs as a graph.
+
+    Returns (Graph, outputs per item, per-item status tensor, plan, workspace);
+    every Graph.launch() transposes the matrices' current contents."""
+    flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+    dev = mats[0].col.device
+    if outs is None:
+        outs = [alloc_outputs(a, perm, a.n_parts > 1, dev) for a in mats]
+    if plan is None:
+        plan = mgt_batch_plan(len(mats), sum(a.nnz for a in mats), sum(a.n_cols for a in mats),
+                              sum(a.n_rows for a in mats), sum(a.n_parts for a in mats),
+                              max(a.nnz for a in mats), max(a.n_cols for a in mats),
+                              mats[0].offset_width, flags)
+    entries, keep = batch_entries(mats, outs, perm, flags)
+    items = make_items(entries)
+    need = mgt_batch_workspace(plan, items)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    status = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+    g = mgt_batch_graph_create(plan, items, workspace, status, keep=(keep, outs, tuple(mats)))
+    return g, outs, status, plan, workspace
 
 
 def view_out_rows(n_rows: int, n_cols: int, n_parts: int, op: int, in_view: int) -> int:

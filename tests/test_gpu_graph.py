@@ -135,3 +135,34 @@ def test_graph_validate_reports_bad_columns():
     h = host(out)
     assert int(status.cpu()[0]) == 0
     assert_matches_oracle(a, h)
+
+
+def test_batch_graph_replays():
+    # one recorded batch submit: replays after in-place input changes, with
+    # outputs and statuses poisoned in between, each against the oracle
+    from paper_2012_06012_amd import mgt
+    base = [gen.tiny(seed=3),
+            gen.random_small(11, n_rows=2000, n_cols=2000, deg_mean=5.0, w_lo=0, w_hi=9, parts=4),
+            gen.random_small(12, n_rows=50, n_cols=70, deg_mean=3.0, w_lo=0, w_hi=3),
+            gen.large(seed=4, scale=10)]
+    base = [b if b.offset_width == 8 else
+            gen.from_arrays(b.n_rows, b.n_cols, b.row_ptr, b.col, np.diff(b.payload_off), b.payload,
+                            8, b.bounds) for b in base]
+    mats = [to_device(a) for a in base]
+    g, outs, status, plan, ws = mgt.batch_graph(mats, perm=True)
+    for k in range(3):
+        cur = [_variant(a, k) for a in base]
+        for d, b in zip(mats, cur):
+            _load(d, b)
+        for o in outs:
+            for v in o.values():
+                if v is not None and v.numel():
+                    v.view(torch.uint8).fill_(0xA5)
+        status.fill_(77)
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        assert (status.cpu().numpy() == 0).all()
+        for b, o in zip(cur, outs):
+            assert_matches_oracle(b, host(o), partitioned=b.n_parts > 1)
+    g.close()

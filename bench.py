@@ -347,6 +347,34 @@ def bench_tiny(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_tune(args):
+    """The autotuner on the two full-size workloads: the default schedule's time
+    against the fastest candidate's (outputs bit-identical for every one)."""
+    import torch
+    from workloads import gen
+    from paper_2012_06012_amd import autotune
+    dev = torch.device("cuda:0")
+    res = {"metric": "autotuned schedule vs the default rule (ms per transpose)", "mode": "tune",
+           "results": {}}
+    for name, mk, part in (("large plain", lambda: gen.large(seed=args.seed, scale=args.scale), False),
+                           ("hetero partitioned", lambda: gen.hetero(seed=args.seed, scale=args.scale),
+                            True)):
+        t0 = time.time()
+        a = mk()
+        d = _device(a, dev)
+        del a
+        log(f"[tune] {name}: ready in {time.time() - t0:.1f}s")
+        plan, r = autotune.autotune(d, partitioned=part, reps=3, use_cache=False)
+        res["results"][name] = {"default_ms": r.default_ms, "default_schedule": r.default_schedule,
+                                "best": r.best, "candidates": len(r.trials),
+                                "all_bit_exact": all(t["bit_exact"] for t in r.trials)}
+        log(f"[tune] {name}: default {r.default_ms:.2f} ms {r.default_schedule}; best "
+            f"{r.best['ms']:.2f} ms {r.best['schedule']} of {len(r.trials)} candidates")
+        del d, plan
+        torch.cuda.empty_cache()
+    print(json.dumps(res), flush=True)
+
+
 def bench_hetero(args):
     """Heterogeneously balanced multigraph, partitioned (R = 256): 2^21 x 2^21,
     2^30 cells, 28-byte payload; sampled output rows checked against the oracle."""
@@ -460,7 +488,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device-to-device copy of this size (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters and measures copy bandwidth)")
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "tiny", "hetero", "involution"],
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "tiny", "hetero", "involution",
+                                       "tune"],
                     default="plain",
                     help="plain: the headline line; batch: many matrices in one mgt_batch_submit "
                          "vs per-matrix launches; serve: the continuous-batching request loop vs "
@@ -490,6 +519,8 @@ def main():
         return bench_hetero(args)
     if args.mode == "involution":
         return bench_involution(args)
+    if args.mode == "tune":
+        return bench_tune(args)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
               "multi-GPU path; see DESIGN.md for how the transpose would shard.", file=sys.stderr)

@@ -149,6 +149,29 @@ int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_
                               int64_t* rdispls, void* workspace, size_t workspace_bytes,
                               int32_t* d_status, hipStream_t stream);
 
+/*
+ * Schedule of a single-matrix plan, for tuning (host only). The transpose is
+ * a few stable partition passes over the column bits followed by a per-bucket
+ * sort; by default the library picks the fewest passes, then the narrowest
+ * finish buckets of about 4,096 cells, and tiles sized for the call.
+ *   pass_bits   largest digit of a bits-mode pass, 1..8 (0: default)
+ *   finish_bits column bits of a finish bucket, 0..10, exactly (-1: default)
+ *   tile_cells  cells per tile: 2048, 4096, 8192 or 16384 (0: default)
+ * The number of passes follows (fewest that cover the remaining bits). A
+ * setting that would need more than four passes gives MGT_EUNSUPPORTED.
+ * *workspace_bytes (may be NULL) receives the workspace the plan now needs:
+ * later calls check against it. Results are the same for every schedule;
+ * only the time differs. Batch and view plans give MGT_EINVAL.
+ */
+int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bits,
+                          int32_t tile_cells, size_t* workspace_bytes);
+
+/* The schedule a call on this plan uses (host only): out[0] passes,
+ * out[1..4] bits of each pass (partition passes: sub-bits below the
+ * partition), out[5] finish bits, out[6] tile cells, out[7] 1 for a
+ * partition-mode first pass. partitioned selects mgt_transpose_partitioned. */
+int mgt_plan_schedule(mgt_plan_t plan, int32_t partitioned, int32_t* out);
+
 /* ------------------------------------------------------------------ batches */
 
 /*

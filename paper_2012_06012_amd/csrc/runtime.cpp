@@ -48,6 +48,15 @@ struct Sched {
   int finish_bits = 0;
 };
 
+// Schedule of a single-matrix plan set by the caller (mgt_plan_set_schedule,
+// e.g. from an autotuner): a cap on the bits of a bits-mode pass, an exact
+// finish width, a tile size; each unset field keeps the rule below.
+struct Tune {
+  int pass_bits = 0;     // 1..8, 0: the environment cap / default
+  int finish_bits = -1;  // 0..10, -1: the rule's choice
+  uint32_t tile = 0;     // 2048..16384 cells, 0: sized for the call
+};
+
 // Schedule caps from the environment: MGT_MAX_PASS_BITS (1..8) bounds the bits
 // of a bits-mode pass and MGT_MAX_FINISH_BITS (0..10) the column bits of a
 // finish bucket. Lower caps trade more passes for smaller fan-outs; tests use
@@ -76,7 +85,7 @@ int passes_for(int B, int first_cap, int mb) {
 // finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
 // parallelism.
 Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
-                    int mb, int mf, bool spread) {
+                    int mb, int mf, bool spread, int force_fb = -1) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -108,6 +117,10 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
     if (L < best_L) { best_L = L; best_fb = fb; }
   }
   if (K <= fb_ideal) { best_fb = K; best_L = 1; }
+  if (force_fb >= 0) {  // a finish width set by the caller
+    best_fb = std::min(force_fb, K);
+    best_L = passes_for(K - best_fb, first_cap, mb);
+  }
   const int B = K - best_fb;
   s.finish_bits = best_fb;
   s.n_levels = best_L;
@@ -124,9 +137,10 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
 }
 
 Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
-                 bool spread) {
-  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, max_pass_bits(), max_finish_bits(),
-                          spread);
+                 bool spread, const Tune* t = nullptr) {
+  const int mb = (t && t->pass_bits > 0) ? t->pass_bits : max_pass_bits();
+  const int ff = (t && t->finish_bits >= 0) ? t->finish_bits : -1;
+  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, mb, max_finish_bits(), spread, ff);
   if (s.n_levels > kMaxLevels)
     s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, kMaxBitsPerPass, kMaxFinishBits, spread);
   return s;
@@ -140,6 +154,7 @@ uint32_t fanout(const Sched& s, int l, int32_t R) {
 struct HostItem {
   mgt_desc d;
   Sched s;
+  uint32_t tile = 0;  // cells per tile set by the caller (single-matrix calls), 0: sized here
   const int64_t* bounds;  // host
   ItemDev dev;
 };
@@ -182,7 +197,8 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   Layout y;
   y.n_vbounds = n_vbounds;
   y.n_items = (uint32_t)items.size();
-  if (items.size() == 1) y.tile_cells = tile_cells_for((uint64_t)items[0].d.nnz);
+  if (items.size() == 1)
+    y.tile_cells = items[0].tile ? items[0].tile : tile_cells_for((uint64_t)items[0].d.nnz);
   const uint64_t tc = y.tile_cells;
   int L = 1;
   for (auto& it : items) L = std::max(L, it.s.n_levels);
@@ -328,6 +344,7 @@ struct mgt_plan_s {
   // Serialises the host part of calls on this plan (staging buffer, upload
   // event, stage-timing events): calls from several threads may share it.
   std::mutex mu;
+  Tune tune;  // single-matrix plans: schedule set by the caller
   // view-operation plans (mgt_view_plan): the operation, the input view, and
   // the descriptor the passes see (virtual rows, sort keys as columns)
   int32_t view_op = -1, column_view = 0;
@@ -638,7 +655,8 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   HostItem& it = items[0];
   it.d = d;
   it.bounds = p->bounds.empty() ? nullptr : p->bounds.data();
-  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned, true);
+  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned, true, &p->tune);
+  it.tile = p->tune.tile;
   if (!partitioned) it.d.n_parts = 1;
   fill_outputs(it.dev, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off, t_payload,
                perm);
@@ -662,12 +680,13 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   return run(p, items, y, ws, d_status, s);
 }
 
-size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned) {
+size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned, const Tune& t) {
   std::vector<HostItem> items(1);
   items[0].d = d;
   if (!partitioned) items[0].d.n_parts = 1;
   items[0].bounds = bounds;
-  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned, true);
+  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned, true, &t);
+  items[0].tile = t.tile;
   std::memset(&items[0].dev, 0, sizeof(ItemDev));
   return make_layout(items).bytes;
 }
@@ -733,8 +752,8 @@ int mgt_plan(const mgt_desc* desc, mgt_plan_t* out, size_t* workspace_bytes) {
   if (desc->part_bounds) p->bounds.assign(desc->part_bounds, desc->part_bounds + desc->n_parts + 1);
   else p->bounds = {0, desc->n_rows};
   p->desc.part_bounds = p->bounds.data();
-  p->ws_plain = single_ws(p->desc, p->bounds.data(), false);
-  p->ws_part = single_ws(p->desc, p->bounds.data(), true);
+  p->ws_plain = single_ws(p->desc, p->bounds.data(), false, p->tune);
+  p->ws_part = single_ws(p->desc, p->bounds.data(), true, p->tune);
   *out = p;
   if (workspace_bytes) *workspace_bytes = std::max(p->ws_plain, p->ws_part);
   return MGT_OK;
@@ -963,6 +982,47 @@ int mgt_batch_graph_create(mgt_plan_t plan, const mgt_item* items, int32_t n_ite
     return st;
   }
   *out = g;
+  return MGT_OK;
+}
+
+int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bits,
+                          int32_t tile_cells, size_t* workspace_bytes) {
+  if (!plan || plan->batch || plan->view_op >= 0) return MGT_EINVAL;
+  if (pass_bits < 0 || pass_bits > kMaxBitsPerPass) return MGT_EINVAL;
+  if (finish_bits < -1 || finish_bits > kMaxFinishBits) return MGT_EINVAL;
+  if (tile_cells != 0 && tile_cells != 2048 && tile_cells != 4096 && tile_cells != 8192 &&
+      tile_cells != 16384)
+    return MGT_EINVAL;
+  std::lock_guard<std::mutex> lock(plan->mu);
+  Tune t;
+  t.pass_bits = pass_bits;
+  t.finish_bits = finish_bits;
+  t.tile = (uint32_t)tile_cells;
+  const mgt_desc& d = plan->desc;
+  for (int part = 0; part < 2; ++part) {  // a setting that needs over kMaxLevels passes is refused
+    const Sched s = make_sched_mb(d.n_cols, d.nnz, d.n_parts, plan->bounds.data(), part != 0,
+                                  pass_bits > 0 ? pass_bits : max_pass_bits(), max_finish_bits(),
+                                  true, finish_bits);
+    if (s.n_levels > kMaxLevels) return MGT_EUNSUPPORTED;
+  }
+  plan->tune = t;
+  plan->ws_plain = single_ws(d, plan->bounds.data(), false, t);
+  plan->ws_part = single_ws(d, plan->bounds.data(), true, t);
+  if (workspace_bytes) *workspace_bytes = std::max(plan->ws_plain, plan->ws_part);
+  return MGT_OK;
+}
+
+int mgt_plan_schedule(mgt_plan_t plan, int32_t partitioned, int32_t* out) {
+  if (!plan || !out || plan->batch || plan->view_op >= 0) return MGT_EINVAL;
+  std::lock_guard<std::mutex> lock(plan->mu);
+  const mgt_desc& d = plan->desc;
+  const Sched s = make_sched(d.n_cols, d.nnz, d.n_parts, plan->bounds.data(), partitioned != 0,
+                             true, &plan->tune);  // as a call with these arguments makes it
+  out[0] = s.n_levels;
+  for (int l = 0; l < kMaxLevels; ++l) out[1 + l] = l < s.n_levels ? s.bits[l] : 0;
+  out[5] = s.finish_bits;
+  out[6] = (int32_t)(plan->tune.tile ? plan->tune.tile : tile_cells_for((uint64_t)d.nnz));
+  out[7] = s.part_mode;
   return MGT_OK;
 }
 

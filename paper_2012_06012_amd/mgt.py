@@ -83,6 +83,8 @@ _lib.mgt_batch_graph_create.argtypes = [_vp, ctypes.POINTER(Item), _i32, _vp, _s
 _lib.mgt_graph_destroy.argtypes = [_vp]
 _i64 = ctypes.c_int64
 _lib.mgt_value_lists_workspace.argtypes = [_i64, ctypes.POINTER(_sz)]
+_lib.mgt_plan_set_schedule.argtypes = [_vp, _i32, _i32, _i32, ctypes.POINTER(_sz)]
+_lib.mgt_plan_schedule.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
 _lib.mgt_coalesce.argtypes = [_i64, _i64, _i32] + [_vp] * 9 + [_sz, _vp]
 _lib.mgt_expand.argtypes = [_i64, _i64, _i64, _i32, _i32] + [_vp] * 7 + [_vp]
 _lib.mgt_counts_to_offsets.argtypes = [_i64, _vp, _i32, _i32, _vp, _vp, _sz, _vp]
@@ -91,14 +93,16 @@ for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_parti
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
            "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
            "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce", "mgt_expand",
-           "mgt_counts_to_offsets", "mgt_batch_graph_create"):
+           "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
+           "mgt_plan_schedule"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
             "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
             "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
             "mgt_graph_launch", "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce",
-            "mgt_expand", "mgt_counts_to_offsets", "mgt_batch_graph_create")
+            "mgt_expand", "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
+            "mgt_plan_schedule")
 
 
 def version() -> str:
@@ -145,6 +149,21 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def set_schedule(self, pass_bits: int = 0, finish_bits: int = -1, tile_cells: int = 0) -> int:
+        """mgt_plan_set_schedule; updates and returns workspace_bytes."""
+        ws = _sz()
+        _check(_lib.mgt_plan_set_schedule(self.handle, pass_bits, finish_bits, tile_cells,
+                                          ctypes.byref(ws)), "mgt_plan_set_schedule")
+        self.workspace_bytes = ws.value
+        return ws.value
+
+    def schedule(self, partitioned: bool = False) -> dict:
+        """The schedule a call uses (mgt_plan_schedule)."""
+        o = (_i32 * 8)()
+        _check(_lib.mgt_plan_schedule(self.handle, 1 if partitioned else 0, o), "mgt_plan_schedule")
+        return {"passes": o[0], "bits": [o[1 + l] for l in range(o[0])], "finish_bits": o[5],
+                "tile_cells": o[6], "partition_pass": bool(o[7])}
 
     def stage_times(self):
         ms = (ctypes.c_float * 64)()

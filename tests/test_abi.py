@@ -263,3 +263,30 @@ def test_value_list_calls_reject_before_launch():
     assert lib.mgt_expand(10, 100, 1 << 40, 8, 4, fake, fake, fake, fake, fake, None, None,
                           None) == -5
     assert lib.mgt_counts_to_offsets(100, None, 4, 8, fake, fake, ws, None) == -1
+
+
+def test_plan_schedule_settings():
+    mgt = _lib()
+    b = [i * (1 << 17) for i in range(65)]
+    p = mgt.mgt_plan(1 << 23, 1 << 23, 1 << 29, 9663557316, 8, b)
+    assert p.schedule() == {"passes": 2, "bits": [8, 8], "finish_bits": 7, "tile_cells": 16384,
+                            "partition_pass": False}
+    assert p.schedule(True)["partition_pass"] and p.schedule(True)["bits"] == [3, 8]
+    ws0 = p.workspace_bytes
+    p.set_schedule(7, 9, 8192)
+    assert p.schedule() == {"passes": 2, "bits": [7, 7], "finish_bits": 9, "tile_cells": 8192,
+                            "partition_pass": False}
+    assert p.schedule(True)["bits"] == [3, 5]          # 17 column bits per partition: 3 + 5 + 9
+    with pytest.raises(mgt.MgtError) as e:            # 20 bits in passes of at most 4: five passes
+        p.set_schedule(4, 3, 0)
+    assert e.value.code == -5
+    assert p.schedule()["finish_bits"] == 9           # a refused setting changes nothing
+    p.set_schedule(5, 8, 0)                            # 15 bits in passes of at most 5: three
+    assert p.schedule()["passes"] == 3 and sum(p.schedule()["bits"]) == 15
+    assert p.set_schedule() == ws0 and p.schedule()["finish_bits"] == 7
+    for bad in ((9, -1, 0), (-1, -1, 0), (0, 11, 0), (0, -2, 0), (0, -1, 1000), (0, -1, 32768)):
+        with pytest.raises(mgt.MgtError):
+            p.set_schedule(*bad)
+    v = mgt.mgt_view_plan(10, 10, 5, 0, 8, None, mgt.VIEW_SWAP, mgt.ROW_VIEW)
+    with pytest.raises(mgt.MgtError):
+        v.set_schedule(8, -1, 0)

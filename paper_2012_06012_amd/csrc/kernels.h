@@ -82,9 +82,6 @@ struct FinishArgs {
   uint64_t g8;                // grid size (multiple of 8)
 };
 
-hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,
-                       uint32_t* hsize0, int32_t* item_status, int32_t* abort_flag,
-                       uint32_t tile_cells, hipStream_t s);
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
                            int32_t* item_status, int32_t* abort_flag, int32_t offset_width,
                            hipStream_t s);

@@ -217,42 +217,6 @@ __device__ __forceinline__ bool aborted(const int32_t* abort_flag) {
 
 // ----------------------------------------------------------------------------- init / validate
 
-__global__ __launch_bounds__(kBlock) void k_init(const ItemDev* items, uint32_t n_items,
-                                                 Seg* segs0, uint32_t* tiles0, uint32_t* hsize0,
-                                                 int32_t* item_status, int32_t* abort_flag,
-                                                 uint32_t tile_cells) {
-  const uint32_t i = blockIdx.x;
-  if (i >= n_items) return;
-  const ItemDev& it = items[i];
-  if (threadIdx.x == 0) {
-    Seg s;
-    s.cell0 = it.cell_base;
-    s.byte0 = it.byte_base;
-    s.len = (uint32_t)it.nnz;
-    s.key_lo = 0;
-    s.key_hi = (uint32_t)it.n_cols;
-    s.item = i;
-    s.bits = (uint32_t)it.bits[0];
-    s.shift = (uint32_t)(it.key_bits - it.bits[0]);
-    s.mode = (uint32_t)it.part_mode;
-    s.pad = 0;
-    segs0[i] = s;
-    const uint32_t tiles = (uint32_t)((it.nnz + tile_cells - 1) / tile_cells);
-    const uint32_t F = it.part_mode ? ((uint32_t)it.n_parts << it.bits[0]) : (1u << it.bits[0]);
-    tiles0[i] = tiles;
-    hsize0[i] = tiles * F;
-    item_status[it.status_index] = MGT_OK;
-    if (i == 0) *abort_flag = 0;
-  }
-  if (it.part_mode && it.xfer_cells) {
-    const uint64_t rr = (uint64_t)it.n_parts * (uint64_t)it.n_parts;
-    for (uint64_t e = threadIdx.x; e < rr; e += kBlock) {
-      it.xfer_cells[e] = 0;
-      it.xfer_bytes[e] = 0;
-    }
-  }
-}
-
 // Device-side data checks (MGT_VALIDATE): offsets start at 0, never decrease
 // and end at nnz / payload_bytes; every column id lies in [0, n_cols); every
 // cell's payload is smaller than 2^32 bytes.
@@ -447,6 +411,15 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     __syncthreads();
   }
   const uint64_t j = tile - a.tstart[si];
+  if (a.pass == 0 && j == 0 && sg.mode && it->xfer_cells) {
+    // the item's transfer matrices start at zero; the first pass's scatter
+    // adds to them after this kernel
+    const uint64_t rr = (uint64_t)R * R;
+    for (uint64_t e = threadIdx.x; e < rr; e += kBlock) {
+      it->xfer_cells[e] = 0;
+      it->xfer_bytes[e] = 0;
+    }
+  }
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   const int ow = a.offset_width;
@@ -1512,6 +1485,14 @@ __global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int3
   }
   if (!it.part_mode || !it.xfer_cells) return;
   const uint32_t R = (uint32_t)it.n_parts;
+  if (it.nnz == 0) {  // no first-pass tile cleared the transfer matrices
+    const uint64_t rr = (uint64_t)R * R;
+    for (uint64_t e = threadIdx.x; e < rr; e += blockDim.x) {
+      it.xfer_cells[e] = 0;
+      it.xfer_bytes[e] = 0;
+    }
+    __syncthreads();
+  }
   // cells / bytes received by each partition s: column sums of X and B
   uint64_t cells = 0, bytes = 0;
   const uint32_t s = threadIdx.x;
@@ -1563,14 +1544,6 @@ hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 #else
-hipError_t launch_init(const ItemDev* items, uint32_t n_items, Seg* segs0, uint32_t* tiles0,
-                       uint32_t* hsize0, int32_t* item_status, int32_t* abort_flag,
-                       uint32_t tile_cells, hipStream_t s) {
-  hipLaunchKernelGGL(G::k_init, grid1(n_items), dim3(G::kBlock), 0, s, items, n_items, segs0, tiles0,
-                     hsize0, item_status, abort_flag, tile_cells);
-  return hipGetLastError();
-}
-
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
                            int32_t* item_status, int32_t* abort_flag, int32_t ow, hipStream_t s) {
   uint64_t gx = (max_len + 1 + G::kBlock * 16 - 1) / (G::kBlock * 16);

@@ -175,6 +175,7 @@ struct Layout {
   uint64_t o_ks[2], o_rk[2], o_pay[2], o_rso = 0;
   // view operations: partition bounds of the matrix, per-cell keys and values
   uint64_t n_vbounds = 0, o_vbounds = 0, o_vkeys = 0, o_vvals = 0;
+  uint64_t o_up_end = 0;  // the uploaded prefix: items, status, bounds, level-0 tables
   uint32_t tile_cells = kTileCells;
   uint64_t bytes = 0;
 };
@@ -260,8 +261,16 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   y.o_abort = take(64);
   y.o_bounds = take(8ull * y.total_bounds);
   if (n_vbounds) y.o_vbounds = take(8ull * n_vbounds);  // uploaded with the bounds
-  for (int l = 0; l <= L; ++l) y.o_segs[l] = take(sizeof(Seg) * y.nseg[l]);
-  for (int l = 0; l < L; ++l) {
+  // the level-0 tables (one segment per item) are filled on the host and
+  // uploaded with the items
+  y.o_segs[0] = take(sizeof(Seg) * y.nseg[0]);
+  y.o_tcnt[0] = take(4ull * y.nseg[0]);
+  y.o_hsz[0] = take(4ull * y.nseg[0]);
+  y.o_tstart[0] = take(8ull * (y.nseg[0] + 1));
+  y.o_hstart[0] = take(8ull * (y.nseg[0] + 1));
+  y.o_up_end = o;
+  for (int l = 1; l <= L; ++l) y.o_segs[l] = take(sizeof(Seg) * y.nseg[l]);
+  for (int l = 1; l < L; ++l) {
     y.o_tcnt[l] = take(4ull * y.nseg[l]);
     y.o_hsz[l] = take(4ull * y.nseg[l]);
     y.o_tstart[l] = take(8ull * (y.nseg[l] + 1));
@@ -405,9 +414,7 @@ struct ViewCall {
 };
 
 // Bytes of the item table and bounds uploaded at the start of a call.
-size_t upload_bytes(const Layout& y) {
-  return y.n_vbounds ? y.o_vbounds + 8ull * y.n_vbounds : y.o_bounds + 8ull * y.total_bounds;
-}
+size_t upload_bytes(const Layout& y) { return y.o_up_end; }
 
 // graph_staging: the call is being recorded into a graph that owns this
 // pinned upload buffer (its contents are read at every replay); the plan's
@@ -449,6 +456,44 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     std::memcpy(H + y.o_items + sizeof(ItemDev) * i, &d, sizeof(ItemDev));
   }
   if (vc) std::memcpy(H + y.o_vbounds, vc->bounds, 8ull * y.n_vbounds);
+  // status words, the abort flag and the level-0 tables: each item is one
+  // segment of columns [0, n_cols) split by its first digit, in tiles of
+  // y.tile_cells cells
+  {
+    int32_t* h_status = (int32_t*)(H + y.o_status);
+    std::memset(H + y.o_abort, 0, 64);
+    uint32_t* h_tcnt = (uint32_t*)(H + y.o_tcnt[0]);
+    uint32_t* h_hsz = (uint32_t*)(H + y.o_hsz[0]);
+    uint64_t* h_tstart = (uint64_t*)(H + y.o_tstart[0]);
+    uint64_t* h_hstart = (uint64_t*)(H + y.o_hstart[0]);
+    uint64_t t_acc = 0, h_acc = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      const HostItem& it = items[i];
+      h_status[i] = MGT_OK;
+      Seg g;
+      g.cell0 = it.dev.cell_base;
+      g.byte0 = it.dev.byte_base;
+      g.len = (uint32_t)it.d.nnz;
+      g.key_lo = 0;
+      g.key_hi = (uint32_t)it.d.n_cols;
+      g.item = i;
+      g.shift = (uint32_t)(it.s.key_bits - it.s.bits[0]);
+      g.bits = (uint32_t)it.s.bits[0];
+      g.mode = (uint32_t)it.s.part_mode;
+      g.pad = 0;
+      std::memcpy(H + y.o_segs[0] + sizeof(Seg) * i, &g, sizeof(Seg));
+      const uint64_t tiles = ((uint64_t)it.d.nnz + y.tile_cells - 1) / y.tile_cells;
+      const uint64_t hs = tiles * fanout(it.s, 0, it.d.n_parts);
+      h_tcnt[i] = (uint32_t)tiles;
+      h_hsz[i] = (uint32_t)hs;
+      h_tstart[i] = t_acc;
+      h_hstart[i] = h_acc;
+      t_acc += tiles;
+      h_acc += hs;
+    }
+    h_tstart[n] = t_acc;
+    h_hstart[n] = h_acc;
+  }
   time_mark(p, s, "start");
   MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
   if (!graph_staging) {
@@ -472,7 +517,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   uint64_t* tsrc = (uint64_t*)(W + y.o_tsrc);
   uint64_t* scan = (uint64_t*)(W + y.o_scan);
 
-  MGT_HIP(launch_init(d_items, n, segs(0), tcnt(0), hsz(0), d_item_status, d_abort, y.tile_cells, s));
   if (vc) {
     ViewArgs v{};
     v.items = d_items;
@@ -498,7 +542,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     for (auto& it : items) max_len = std::max<uint64_t>(max_len, (uint64_t)std::max(it.d.n_rows, it.d.nnz));
     MGT_HIP(launch_validate(d_items, n, max_len, d_item_status, d_abort, ow, s));
   }
-  MGT_HIP(launch_scan(tcnt(0), tstart(0), hsz(0), hstart(0), nullptr, y.nseg[0], scan, s));
   time_mark(p, s, "init");
 
   const int L = y.L;

@@ -70,6 +70,7 @@ struct ChildArgs {
 
 struct FinishArgs {
   const ItemDev* items;
+  uint32_t n_items;           // <= nbuckets: every item has at least one bucket
   const Seg* buckets;
   uint32_t nbuckets;
   const uint2* ks_in;
@@ -78,6 +79,8 @@ struct FinishArgs {
   const uint32_t* rso_in;     // (row, cell index, payload offset in pay_in) records of the
                               // last pass, read in place of rk_in, or null
   const int32_t* abort_flag;
+  const int32_t* item_status;
+  int32_t* d_status;          // the caller's status words (may be null), written with the tails
   int32_t offset_width;
   uint64_t g8;                // grid size (multiple of 8)
 };
@@ -114,9 +117,6 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s);  // records-only pass
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
-hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,
-                        const int32_t* abort_flag, int32_t ow, int32_t* d_status, hipStream_t s);
-
 // Scratch needed by launch_scan for n_max elements (bytes).
 inline uint64_t scan_scratch_bytes(uint64_t n_max) {
   return 2 * 8 * ((n_max + kScanBlock - 1) / kScanBlock + 1) + 64;

@@ -1230,6 +1230,83 @@ __global__ __launch_bounds__(kBlock) void k_view_keys(ViewArgs a) {
 
 // ----------------------------------------------------------------------------- finish
 
+// An item's tails, by one whole block: the caller's status word,
+// t_row_ptr[n_cols] and t_payload_off[nnz], and for a partitioned item the
+// partition offsets (column sums of X and B, scanned) and both displacement
+// matrices (Section 2 step 2; Alltoallv displacements). Partitions are split
+// in runs of `per` per thread, up to kMaxParts / kBlock.
+constexpr int kTailPer = (kMaxParts + kBlock - 1) / kBlock;
+__device__ void item_tails(const ItemDev& it, uint32_t i, const int32_t* item_status,
+                           const int32_t* abort_flag, int ow, int32_t* d_status, uint64_t* red) {
+  if (d_status && threadIdx.x == 0) {
+    const int32_t st = item_status[i];
+    d_status[i] = (st == MGT_OK && *abort_flag) ? MGT_ECANCELED : st;
+  }
+  if (aborted(abort_flag)) return;
+  if (threadIdx.x == 0) {
+    st_off(it.t_row_ptr, (uint64_t)it.n_cols, it.nnz, ow);
+    if (it.t_poff) st_off(it.t_poff, (uint64_t)it.nnz, it.payload_bytes, ow);
+  }
+  if (!it.part_mode || !it.xfer_cells) return;
+  const uint32_t R = (uint32_t)it.n_parts;
+  const uint64_t rr = (uint64_t)R * R;
+  if (it.nnz == 0) {  // no first-pass tile cleared the transfer matrices
+    for (uint64_t e = threadIdx.x; e < rr; e += kBlock) {
+      it.xfer_cells[e] = 0;
+      it.xfer_bytes[e] = 0;
+    }
+    __syncthreads();
+  }
+  const uint32_t per = (R + kBlock - 1) / kBlock;  // <= kTailPer
+  const uint32_t s0 = threadIdx.x * per;
+  uint64_t cs[kTailPer], bs[kTailPer], cells = 0, bytes = 0;
+#pragma unroll
+  for (int k = 0; k < kTailPer; ++k) {  // cells / bytes received by partition s0 + k
+    cs[k] = bs[k] = 0;
+    const uint32_t s = s0 + (uint32_t)k;
+    if ((uint32_t)k < per && s < R)
+      for (uint32_t r = 0; r < R; ++r) {
+        cs[k] += (uint64_t)it.xfer_cells[(uint64_t)r * R + s];
+        bs[k] += (uint64_t)it.xfer_bytes[(uint64_t)r * R + s];
+      }
+    cells += cs[k];
+    bytes += bs[k];
+  }
+  uint64_t tc, tb;
+  uint64_t ec = block_excl_scan<kNW>(cells, red, tc);
+  uint64_t eb = block_excl_scan<kNW>(bytes, red, tb);
+#pragma unroll
+  for (int k = 0; k < kTailPer; ++k) {
+    const uint32_t s = s0 + (uint32_t)k;
+    if ((uint32_t)k < per && s < R) {
+      if (it.part_cell_off) it.part_cell_off[s] = (int64_t)ec;
+      if (it.part_byte_off) it.part_byte_off[s] = (int64_t)eb;
+    }
+    ec += cs[k];
+    eb += bs[k];
+  }
+  if (threadIdx.x == 0) {
+    if (it.part_cell_off) it.part_cell_off[R] = (int64_t)tc;
+    if (it.part_byte_off) it.part_byte_off[R] = (int64_t)tb;
+  }
+  for (uint32_t s = threadIdx.x; s < R; s += kBlock) {
+    if (it.sdispls) {  // row s of X scanned along destinations
+      int64_t acc = 0;
+      for (uint32_t d = 0; d < R; ++d) {
+        it.sdispls[(uint64_t)s * R + d] = acc;
+        acc += it.xfer_cells[(uint64_t)s * R + d];
+      }
+    }
+    if (it.rdispls) {  // column s of X scanned along sources
+      int64_t acc = 0;
+      for (uint32_t r = 0; r < R; ++r) {
+        it.rdispls[(uint64_t)s * R + r] = acc;
+        acc += it.xfer_cells[(uint64_t)r * R + s];
+      }
+    }
+  }
+}
+
 // kGather: the last pass moved records only; each cell's payload is read
 // from the previous level buffer at the bucket's src0 plus the cell's stored
 // offset. Otherwise payloads follow the records in the same level buffer.
@@ -1242,10 +1319,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
   __shared__ uint32_t s_red[kNW + 1];
   __shared__ uint64_t s_red64[kNW + 1];
-  if (aborted(a.abort_flag)) return;
   // Gathering finishes run their buckets in plain column order on all XCDs
   // at once: the buckets in flight then read from one or two source segments
   // (tens of MB, resident in the memory-side cache) instead of eight.
+  // Block i < n_items also writes item i's tails. This comes first: after an
+  // abort the bucket table below was never written, and only the status
+  // words are.
+  if (blockIdx.x < a.n_items)
+    item_tails(a.items[blockIdx.x], blockIdx.x, a.item_status, a.abort_flag, a.offset_width,
+               a.d_status, s_red64);
+  if (aborted(a.abort_flag)) return;
   const uint64_t bk = kGather ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.g8);
   if (bk >= a.nbuckets) return;
   const Seg sg = a.buckets[bk];
@@ -1469,65 +1552,6 @@ __global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
 
 // ----------------------------------------------------------------------------- tails
 
-__global__ __launch_bounds__(1024) void k_tails(const ItemDev* items, const int32_t* item_status,
-                                                const int32_t* abort_flag, int ow,
-                                                int32_t* d_status) {
-  __shared__ uint64_t red[1024 / kWave + 1];
-  if (d_status && threadIdx.x == 0) {  // the caller's status word of this item
-    const int32_t st = item_status[blockIdx.x];
-    d_status[blockIdx.x] = (st == MGT_OK && *abort_flag) ? MGT_ECANCELED : st;
-  }
-  if (aborted(abort_flag)) return;
-  const ItemDev& it = items[blockIdx.x];
-  if (threadIdx.x == 0) {
-    st_off(it.t_row_ptr, (uint64_t)it.n_cols, it.nnz, ow);
-    if (it.t_poff) st_off(it.t_poff, (uint64_t)it.nnz, it.payload_bytes, ow);
-  }
-  if (!it.part_mode || !it.xfer_cells) return;
-  const uint32_t R = (uint32_t)it.n_parts;
-  if (it.nnz == 0) {  // no first-pass tile cleared the transfer matrices
-    const uint64_t rr = (uint64_t)R * R;
-    for (uint64_t e = threadIdx.x; e < rr; e += blockDim.x) {
-      it.xfer_cells[e] = 0;
-      it.xfer_bytes[e] = 0;
-    }
-    __syncthreads();
-  }
-  // cells / bytes received by each partition s: column sums of X and B
-  uint64_t cells = 0, bytes = 0;
-  const uint32_t s = threadIdx.x;
-  if (s < R)
-    for (uint32_t r = 0; r < R; ++r) {
-      cells += (uint64_t)it.xfer_cells[(uint64_t)r * R + s];
-      bytes += (uint64_t)it.xfer_bytes[(uint64_t)r * R + s];
-    }
-  uint64_t tc, tb;
-  const uint64_t ec = block_excl_scan<1024 / kWave>(cells, red, tc);
-  const uint64_t eb = block_excl_scan<1024 / kWave>(bytes, red, tb);
-  if (s < R) {
-    if (it.part_cell_off) it.part_cell_off[s] = (int64_t)ec;
-    if (it.part_byte_off) it.part_byte_off[s] = (int64_t)eb;
-  }
-  if (s == 0) {
-    if (it.part_cell_off) it.part_cell_off[R] = (int64_t)tc;
-    if (it.part_byte_off) it.part_byte_off[R] = (int64_t)tb;
-  }
-  if (s < R && it.sdispls) {  // row s of X scanned along destinations
-    int64_t acc = 0;
-    for (uint32_t d = 0; d < R; ++d) {
-      it.sdispls[(uint64_t)s * R + d] = acc;
-      acc += it.xfer_cells[(uint64_t)s * R + d];
-    }
-  }
-  if (s < R && it.rdispls) {  // column s of X scanned along sources
-    int64_t acc = 0;
-    for (uint32_t r = 0; r < R; ++r) {
-      it.rdispls[(uint64_t)s * R + r] = acc;
-      acc += it.xfer_cells[(uint64_t)r * R + s];
-    }
-  }
-}
-
 }  // namespace MGT_GEO_NS
 
 // ----------------------------------------------------------------------------- launchers
@@ -1612,13 +1636,6 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
     if (a.rso_in) hipLaunchKernelGGL(G::k_finish<true>, grid1(a.g8), dim3(G::kBlock), 0, s, a);
     else hipLaunchKernelGGL(G::k_finish<false>, grid1(a.g8), dim3(G::kBlock), 0, s, a);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_tails(const ItemDev* items, uint32_t n_items, const int32_t* item_status,
-                        const int32_t* abort_flag, int32_t ow, int32_t* d_status, hipStream_t s) {
-  hipLaunchKernelGGL(G::k_tails, grid1(n_items), dim3(1024), 0, s, items, item_status, abort_flag, ow,
-                     d_status);
   return hipGetLastError();
 }
 

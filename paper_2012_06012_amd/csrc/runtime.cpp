@@ -606,6 +606,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   }
   FinishArgs f{};
   f.items = d_items;
+  f.n_items = n;
   f.buckets = segs(L);
   f.nbuckets = (uint32_t)y.nseg[L];
   const int bl = (L - 1) & 1;
@@ -615,12 +616,13 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.rso_in = L >= 2 ? (const uint32_t*)(W + y.o_rso) : nullptr;
   if (f.rso_in) f.rk_in = nullptr;
   f.abort_flag = d_abort;
+  f.item_status = d_item_status;
+  f.d_status = d_status;
   f.offset_width = ow;
   f.g8 = align_up(y.nseg[L], 8);
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
-  MGT_HIP(launch_tails(d_items, n, d_item_status, d_abort, ow, d_status, s));
-  time_mark(p, s, "tails");
+
   return MGT_OK;
 }
 

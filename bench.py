@@ -66,10 +66,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "abfd6d018631b6532f2492dcbea726b3a09ca87da5dd54b2cb17cfd6855beb80",
-                       "fetch_kib": 6534643.7, "write_kib": 17864178.2},
-    "k_finish": {"sources_sha256": "abfd6d018631b6532f2492dcbea726b3a09ca87da5dd54b2cb17cfd6855beb80",
-                 "fetch_kib": 27409435, "write_kib": 18591027},
+    "k_pass_scatter": {"sources_sha256": "6f5c557b50ade2378653447f242ada1115419127259e96ec3b1ae4b663ff4d0d",
+                       "fetch_kib": 6535133.3, "write_kib": 17859700.4},
+    "k_finish": {"sources_sha256": "6f5c557b50ade2378653447f242ada1115419127259e96ec3b1ae4b663ff4d0d",
+                 "fetch_kib": 27566940, "write_kib": 18585103},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

@@ -342,8 +342,9 @@ int mgt_counts_to_offsets(int64_t nnz, const uint32_t* counts, int32_t value_byt
  * MGT_EINVAL). Nothing runs at creation. Each mgt_graph_launch runs the whole
  * call on `stream`, reading the inputs as they are at that time; the buffers
  * must stay allocated while the graph exists, and launches that overlap on
- * one workspace race. The plan may be destroyed after creation. The graph
- * clears its own status and counters with kernels (it records no memset).
+ * one workspace race. The plan may be destroyed after creation. Each replay
+ * re-uploads the graph's descriptor copy (status words and first-pass tables
+ * included) and clears counters with kernel stores (it records no memset).
  */
 typedef struct mgt_graph_s* mgt_graph_t;
 

@@ -66,10 +66,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "6f5c557b50ade2378653447f242ada1115419127259e96ec3b1ae4b663ff4d0d",
-                       "fetch_kib": 6535133.3, "write_kib": 17859700.4},
-    "k_finish": {"sources_sha256": "6f5c557b50ade2378653447f242ada1115419127259e96ec3b1ae4b663ff4d0d",
-                 "fetch_kib": 27566940, "write_kib": 18585103},
+    "k_pass_scatter": {"sources_sha256": "a7cd6210b0464ed60899f6ddc125e09fbf7301e51a481530f4d3eb0501877f84",
+                       "fetch_kib": 6534413.2, "write_kib": 17859884.3},
+    "k_finish": {"sources_sha256": "a7cd6210b0464ed60899f6ddc125e09fbf7301e51a481530f4d3eb0501877f84",
+                 "fetch_kib": 27581925, "write_kib": 18585075},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

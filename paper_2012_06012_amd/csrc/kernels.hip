@@ -215,6 +215,8 @@ __device__ __forceinline__ bool aborted(const int32_t* abort_flag) {
   return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
+// (the 512-thread copy of this file needs only the records-only scatter)
+#ifndef MGT_WIDE
 // ----------------------------------------------------------------------------- init / validate
 
 // Device-side data checks (MGT_VALIDATE): offsets start at 0, never decrease
@@ -503,6 +505,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     if (tot >> 32) raise_status(a.item_status, a.abort_flag, it->status_index, MGT_EUNSUPPORTED);
   }
 }
+
+#endif  // MGT_WIDE
 
 // ----------------------------------------------------------------------------- shared sub-chunk sort
 
@@ -1166,6 +1170,8 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   }
 }
 
+// (the 512-thread copy of this file needs only the records-only scatter)
+#ifndef MGT_WIDE
 // ----------------------------------------------------------------------------- view keys
 
 // Sort key and carried value of every cell for LocalTranspose and ViewSwap
@@ -1550,7 +1556,8 @@ __global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
   }
 }
 
-// ----------------------------------------------------------------------------- tails
+#endif  // MGT_WIDE
+
 
 }  // namespace MGT_GEO_NS
 

@@ -235,8 +235,6 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
   for (int l = 0; l < L; ++l) {
     uint64_t tiles = 0, hist = 0;
     for (auto& it : items) {
-      uint64_t ns = it.dev.seg_base[l];  // not used directly
-      (void)ns;
       uint64_t segs_item = 1;
       for (int q = 0; q < l; ++q) segs_item *= fanout(it.s, q, it.d.n_parts);
       const uint64_t t = ((uint64_t)it.d.nnz + tc - 1) / tc + (l ? segs_item : 0);
@@ -377,7 +375,7 @@ int ensure_staging(mgt_plan_s* p, size_t bytes) {
     p->upload_pending = false;
   }
   if (p->staging_bytes >= bytes) return MGT_OK;
-  if (p->staging) hipHostFree(p->staging);
+  if (p->staging) (void)hipHostFree(p->staging);
   p->staging = nullptr;
   p->staging_bytes = 0;
   if (hipHostMalloc(&p->staging, bytes, hipHostMallocDefault) != hipSuccess) return MGT_ENOMEM;
@@ -395,7 +393,7 @@ void time_mark(mgt_plan_s* p, hipStream_t s, const char* name) {
     t.names.push_back(name);
   }
   t.names[t.used] = name;
-  hipEventRecord(t.ev[t.used], s);
+  (void)hipEventRecord(t.ev[t.used], s);
   ++t.used;
 }
 
@@ -679,8 +677,8 @@ int record_graph(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, v
     g->exec = nullptr;
     st = MGT_EHIP;
   }
-  if (graph) hipGraphDestroy(graph);
-  hipStreamDestroy(s);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(s);
   return st;
 }
 
@@ -806,10 +804,10 @@ int mgt_plan(const mgt_desc* desc, mgt_plan_t* out, size_t* workspace_bytes) {
 
 int mgt_plan_destroy(mgt_plan_t p) {
   if (!p) return MGT_EINVAL;
-  if (p->upload_pending) hipEventSynchronize(p->upload_done);
-  if (p->staging) hipHostFree(p->staging);
-  if (p->upload_done) hipEventDestroy(p->upload_done);
-  for (auto e : p->timing.ev) hipEventDestroy(e);
+  if (p->upload_pending) (void)hipEventSynchronize(p->upload_done);
+  if (p->staging) (void)hipHostFree(p->staging);
+  if (p->upload_done) (void)hipEventDestroy(p->upload_done);
+  for (auto e : p->timing.ev) (void)hipEventDestroy(e);
   delete p;
   return MGT_OK;
 }
@@ -942,8 +940,8 @@ int mgt_graph_launch(mgt_graph_t g, hipStream_t stream) {
 
 int mgt_graph_destroy(mgt_graph_t g) {
   if (!g) return MGT_EINVAL;
-  if (g->exec) hipGraphExecDestroy(g->exec);
-  if (g->staging) hipHostFree(g->staging);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->staging) (void)hipHostFree(g->staging);
   delete g;
   return MGT_OK;
 }

@@ -90,6 +90,26 @@ def kernel_sources_digest() -> str:
     return h.hexdigest()
 
 
+def host_info() -> dict:
+    """CPU count, the CPUs this process may use, CPU model and RAM of the host."""
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": model, "ram_gib": ram}
+
+
 def measured_traffic(kname: str, args):
     m = MEASURED_TRAFFIC.get(kname)
     if (m is None or args.partitioned or args.scale or args.seed
@@ -639,7 +659,7 @@ def main():
         exact = bool(ok)
         log(f"[bench] sampled parity: {exact}")
 
-    cpu = None
+    cpu = cpu_mt = None
     if not args.no_cpu:
         import oracle
         # bounded sample (about 10 s single-threaded at full size): the first
@@ -654,8 +674,19 @@ def main():
         cs = time.perf_counter() - c0
         cpu = {"value": sub.nnz / cs, "unit": "cells/s", "cores": 1, "kind": "oracle",
                "sample": f"first {rows} rows ({sub.nnz} cells, {sub.payload_bytes} payload bytes) "
-                         f"of the same matrix, all {a.n_cols} columns; {cs:.1f} s single-threaded"}
+                         f"of the same matrix, all {a.n_cols} columns; {cs:.1f} s single-threaded",
+               "host": host_info()}
         log(f"[bench] cpu oracle: {cpu['value']:.3e} cells/s")
+        # the multi-threaded scan-based baseline on the same sample
+        nt = oracle.host_threads()
+        c0 = time.perf_counter()
+        oracle.transpose_mt(sub, nt, perm=False)
+        cm = time.perf_counter() - c0
+        cpu_mt = {"value": sub.nnz / cm, "unit": "cells/s", "cores": nt,
+                  "kind": "multi-threaded scan-based transpose (per-thread column counts)",
+                  "sample": f"the same {sub.nnz} cells; {cm:.2f} s on {nt} threads",
+                  "host": host_info()}
+        log(f"[bench] cpu multi-threaded: {cpu_mt['value']:.3e} cells/s on {nt} threads")
 
     res = {
         "metric": "cells/s (plain transpose, bit-exact) and % of HBM peak",
@@ -685,6 +716,7 @@ def main():
                      "unit": "GB/s", "frac": dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                      "traffic": traffic, "bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms},
         "cpu_baseline": cpu,
+        "cpu_baseline_mt": cpu_mt,
     }
     print(json.dumps(res), flush=True)
 

@@ -6,8 +6,10 @@ counting-sort transpose written from the paper's definitions) and adds two
 pure-Python/numpy cross-checks: ``brute`` (sort every cell by its transposed
 key) and ``staged`` (a rank-by-rank simulation of the paper's staged
 algorithm), ``views`` (the Section 3 LocalTranspose and ViewSwap on their
-own) and ``values`` (XCSR value lists against repeated cells, Section 2). The
-GPU library shares no code with anything here.
+own) and ``values`` (XCSR value lists against repeated cells, Section 2).
+``scantrans.c`` is the multi-threaded CPU baseline the benchmark reports
+beside the oracle (``transpose_mt``); the tests pin it against ``oracle.c``.
+The GPU library shares no code with anything here.
 """
 from __future__ import annotations
 
@@ -22,6 +24,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_MT_SRC = os.path.join(_HERE, "scantrans.c")
+_MT_LIB = os.path.join(_HERE, "libscantrans.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -5
 FAULT_NONE, FAULT_UNSTABLE, FAULT_SHORT_COPY, FAULT_INDEX_FOR_ROW, FAULT_SWAP_XFER, \
@@ -35,6 +39,12 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", _SRC,
                                "-o", tmp])
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_MT_LIB) or \
+            os.path.getmtime(_MT_LIB) < os.path.getmtime(_MT_SRC):
+        tmp = _MT_LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-std=gnu99", "-Wall", "-fPIC", "-shared", "-pthread",
+                               _MT_SRC, "-o", tmp])
+        os.replace(tmp, _MT_LIB)
     return _LIB
 
 
@@ -120,6 +130,45 @@ def transpose(a) -> Transposed:
     if st != OK:
         raise OracleError(st)
     return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)
+
+
+_mt_lib = None
+
+
+def host_threads(cap: int = 16) -> int:
+    """CPUs this process may run on, at most `cap`."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, cap))
+
+
+def transpose_mt(a, threads: int, perm: bool = True) -> Transposed:
+    """The multi-threaded scan-based CPU baseline (``scantrans.c``); same
+    result as ``transpose``."""
+    global _mt_lib
+    if _mt_lib is None:
+        if not os.path.exists(_MT_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_MT_LIB)
+        i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        lib.mgs_transpose.argtypes = [i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
+        lib.mgs_transpose.restype = ctypes.c_int
+        _mt_lib = lib
+    dt = np.int32 if a.offset_width == 4 else np.int64
+    nnz = a.nnz
+    t_row_ptr = np.empty(a.n_cols + 1, dtype=dt)
+    t_col = np.empty(nnz, dtype=np.int32)
+    t_poff = np.empty(nnz + 1, dtype=dt)
+    t_payload = np.empty(a.payload_bytes, dtype=np.uint8)
+    pm = np.empty(nnz, dtype=np.uint32) if perm else None
+    st = _mt_lib.mgs_transpose(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col),
+                               _p(a.payload_off), _p(a.payload), _p(t_row_ptr), _p(t_col),
+                               _p(t_poff), _p(t_payload), _p(pm), int(threads))
+    if st != OK:
+        raise OracleError(st)
+    return Transposed(t_row_ptr, t_col, t_poff, t_payload, pm)
 
 
 def partition_counts(a) -> PartitionCounts:

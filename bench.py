@@ -175,12 +175,16 @@ def bench_batch(args):
         waves.append(cur)
     log(f"[batch] {n_items} matrices in {len(waves)} waves (budget {args.batch_budget:.3g} B)")
     tot_cells, ms_b_tot, ms_g_tot, ms_p_tot, same_all = 0, 0.0, 0.0, 0.0, True
+    tot_bytes = 0  # algorithmic bytes of every matrix (inputs read once, outputs written once)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for wi, idx in enumerate(waves):
         t0 = time.time()
         mats = []
         for i in idx:
-            mats.append(_device(gen.batch_item(args.seed, i, 1e3, args.batch_n_hi), dev))
+            h = gen.batch_item(args.seed, i, 1e3, args.batch_n_hi)
+            tot_bytes += h.algorithmic_bytes()
+            mats.append(_device(h, dev))
+            del h
         cells = sum(a.nnz for a in mats)
         log(f"[batch] wave {wi}: {len(mats)} matrices, {cells} cells, ready in {time.time() - t0:.1f}s")
         outs, status, plan, ws = mgt.batch_transpose(mats)  # warm-up, allocations
@@ -252,6 +256,9 @@ def bench_batch(args):
            "ms_batched": ms_b_tot, "ms_batched_graph": ms_g_tot, "ms_per_matrix_plain": ms_p_tot,
            "cells_per_s_batched": tot_cells / (ms_b_tot * 1e-3),
            "cells_per_s_plain": tot_cells / (ms_p_tot * 1e-3), "speedup": ms_p_tot / ms_b_tot,
+           "algorithmic_bytes": tot_bytes,
+           "hbm_frac_batched": tot_bytes / (ms_b_tot * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "hbm_frac_plain": tot_bytes / (ms_p_tot * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "bit_exact_batched_vs_plain": bool(same_all),
            "config": {"workload": f"batch of matrices, n log-uniform 1e3-{args.batch_n_hi:.0e}, "
                                   "mean degree U{8..64}, payload U{0..16} bytes per matrix",
@@ -276,6 +283,7 @@ def bench_serve(args):
                                  w_hi=width, offset_width=8, bounds=gen.equal_bounds(n, min(r, n))))
     pool = [_device(a, dev) for a in host]
     pool_cells = sum(a.nnz for a in host)
+    pool_bytes = [a.algorithmic_bytes(partitioned=a.n_parts > 1) for a in host]
     del host
     log(f"[serve] pool of {pool_n} inputs, {pool_cells} cells, {time.time() - t0:.1f}s")
     n_req = args.serve_requests
@@ -302,6 +310,8 @@ def bench_serve(args):
     bex = serve.GpuExecutor(n_slots=2, max_items=64, batch_cells=1 << 26)
     pex = serve.PlainExecutor()
     warm = args.serve_warmup  # per rate: device allocations are made and cached there
+    bytes_per_cell = (sum(pool_bytes[i % pool_n] for i in range(n_req)) /
+                      max(1, sum(pool[i % pool_n].nnz for i in range(n_req))))
     for frac in (0.5, 0.7, 0.9, 1.2):
         rate = frac * mu
         Server(bex, budget, max_batch=32, n_slots=2, on_done=release).run(make(rate)[:warm])
@@ -309,6 +319,8 @@ def bench_serve(args):
         Server(pex, budget, max_batch=1, n_slots=1, on_done=release).run(make(rate)[:warm])
         sp = Server(pex, budget, max_batch=1, n_slots=1, on_done=release).run(make(rate))
         out[f"{frac}mu"] = {"batched": sb.summary(), "plain": sp.summary()}
+        for v in out[f"{frac}mu"].values():  # algorithmic bytes per cell of this request stream
+            v["hbm_frac"] = v["cells_per_s"] * bytes_per_cell / 1e9 / HBM_PEAK_GBS
         log(f"[serve] rate {rate:.1f}/s: batched {sb.summary()} plain {sp.summary()}")
     res = {"metric": "served p50/p99 latency and sustained cells/s, batched vs plain",
            "mode": "serve", "requests": n_req, "warmup_requests": warm,

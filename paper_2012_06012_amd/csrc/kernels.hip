@@ -214,6 +214,12 @@ __device__ __forceinline__ void raise_status(int32_t* item_status, int32_t* abor
 __device__ __forceinline__ bool aborted(const int32_t* abort_flag) {
   return __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
+// Whether this call's records are packed: the host allows it (pk_on) and the
+// first histogram found every payload size within 32 - pk_shift bits (it sets
+// no_pack otherwise). Uniform over the grid.
+__device__ __forceinline__ bool packed_records(int32_t pk_on, const int32_t* no_pack) {
+  return pk_on && __hip_atomic_load(no_pack, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
 
 // (the 512-thread copy of this file needs only the records-only scatter)
 #ifndef MGT_WIDE
@@ -427,6 +433,9 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   const int ow = a.offset_width;
   uint64_t mybytes = 0;
   constexpr uint64_t kStride = (uint64_t)kBlock * kBatch;
+  // sizes from 2^(32 - pk_shift) bytes on cannot be packed beside a column
+  const uint64_t pk_lim = 1ull << (32 - a.pk_shift);
+  bool too_wide = false;
   if (a.pass == 0) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
     const int32_t* col = it->col;
@@ -434,9 +443,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
     const int lg = ow == 8 ? 3 : 2;
     const int32_t fw = it->fixed_w;
     // the tile's bytes exactly; below 2^32 they make every low-word size exact
-    if (fw >= 0)
+    if (fw >= 0) {
       mybytes = threadIdx.x == 0 ? (c_end - c_begin) * (uint64_t)fw : 0;
-    else
+      too_wide = (uint64_t)fw >= pk_lim;
+    } else
       mybytes = threadIdx.x == 0 ? ld_full(poff, kbase + c_end, lg) - ld_full(poff, kbase + c_begin, lg) : 0;
     // (every loop below has the same trip count on all lanes: the run
     // aggregation works on whole waves)
@@ -472,9 +482,14 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
         const uint32_t sz = p1[q] - p0[q];
         const uint32_t d = act ? digit_of(key[q], sg, s_lb, s_ot, osh, R) : 0u;
         hist_add_runs(act, d, sz, s_cnt, s_byt);
+        too_wide |= act && (uint64_t)sz >= pk_lim;
       }
     }
+    if (a.pk_on && too_wide) gm(a.no_pack)[0] = 1;
   } else {
+    // pass 1 reads the first pass's records, packed or not (uniform)
+    const bool pk = packed_records(a.pk_on, a.no_pack);
+    const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
     for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
       const uint64_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
@@ -486,9 +501,11 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const bool act = c + (uint64_t)q * kBlock < c_end;
-        const uint32_t d = act ? digit_of(ks[q].x, sg, s_lb, s_ot, osh, R) : 0u;
-        hist_add_runs(act, d, ks[q].y, s_cnt, s_byt);
-        if (act) mybytes += ks[q].y;
+        const uint32_t key = pk ? ks[q].x & pk_mask : ks[q].x;
+        const uint32_t sz = pk ? ks[q].x >> a.pk_shift : ks[q].y;
+        const uint32_t d = act ? digit_of(key, sg, s_lb, s_ot, osh, R) : 0u;
+        hist_add_runs(act, d, sz, s_cnt, s_byt);
+        if (act) mybytes += sz;
       }
     }
   }
@@ -908,6 +925,31 @@ __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const 
   }
 }
 
+// Packed records (a single matrix with one records-only pass, no perm): after
+// the first pass a cell is (column | size << pk_shift, row), after the second
+// (column | size << pk_shift, row, payload offset as two words).
+__device__ __forceinline__ void load_sub_pk8(SubLoad& S, const uint2* ks, uint64_t pos0, uint32_t n) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
+    const uint2 x = ks[pos0 + i];
+    S.a[r] = x.x; S.c[r] = x.y;
+  }
+}
+__device__ __forceinline__ void load_sub_pk16(SubLoad& S, const uint32_t* rso, uint64_t pos0,
+                                              uint32_t n) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
+    const v4u y = gm((const v4u*)rso)[pos0 + i];
+    S.a[r] = y.x; S.c[r] = y.y; S.e[r] = y.z; S.f[r] = y.w;
+  }
+}
+constexpr int kFieldsPk8 = 1 | 4;
+constexpr int kFieldsPk16 = 1 | 4 | 16 | 64;
+
 // Payload sizes of a pass-0 sub-chunk from the low offset words: each cell's
 // size is the next cell's offset minus its own (the next cell is the next
 // lane, or lane 0 of the next register, or the wave's `pend`).
@@ -923,26 +965,15 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
   }
 }
 
-// One instance per kind of pass, so the loop has no branch between the two
-// load layouts: a branch there makes the compiler reconcile the registers of
-// in-flight loads at the join, which waits for them.
-// The records-only pass keeps no byte prefix and no byte cursors, and only a
-// bits-mode fan-out: under 53 KB of LDS and 168 VGPRs, so three workgroups fit
-// on a CU instead of two.
-// kVal (first pass only): every cell carries a value of its own (item vval)
-// in place of its row id, so no rows are expanded.
-template <bool kPass0, bool kDefer, bool kVal>
-__global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scatter(PassArgs a) {
-  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
-  __shared__ SortLdsT<kFan, !kDefer> L;
-  __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
-  __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
-  __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
-  __shared__ uint16_t s_ot[kPass0 ? kOwnerT + 1 : 1];   // their coarse owner table
-  __shared__ Seg s_seg;
-  __shared__ uint32_t s_si, s_extra;
-  __shared__ uint32_t s_red[kNW + 1];
-  if (aborted(a.abort_flag)) return;
+// kPk: packed records (see load_sub_pk8); only the first pass of a plain
+// (not view) call and the records-only pass have a packed form.
+template <bool kPass0, bool kDefer, bool kVal, bool kPk, class Lds>
+__device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t* s_rc,
+                                             uint64_t* s_rb, int32_t* s_lb, uint16_t* s_ot,
+                                             Seg& s_seg, uint32_t& s_si, uint32_t& s_extra,
+                                             uint32_t* s_red) {
+  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;
+  const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
   {
@@ -966,7 +997,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   constexpr bool pass0 = kPass0;
-  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : kFieldsPass0) : kFieldsRec;
+  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : kFieldsPass0) : (kPk ? kFieldsPk8 : kFieldsRec);
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
   const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
   // item fields used in the loop, read once
@@ -1010,6 +1041,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
     if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw,
                                         kVal ? it->vval : nullptr);
+    else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c_begin, n0);
     else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c_begin, n0);
     settle<kFields>(cur, nxt);  // the loop's first iteration then starts from settled registers too
   }
@@ -1049,7 +1081,12 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
-        key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
+        if constexpr (kPk) {
+          key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> a.pk_shift : 0u;
+          row[r] = cur.c[r]; idx[r] = 0u;
+        } else {
+          key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
+        }
       }
       src_sub += sub_src_prefix(sz, src, s_red);
     }
@@ -1065,6 +1102,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
       if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
                                           kVal ? it->vval : nullptr);
+      else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
     }
     sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
@@ -1085,11 +1123,16 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
         if (i < n) {
           const uint32_t d = L.dig[i];
           const uint64_t cd = seg_out + s_rc[d] + (i - L.wc[d * kNW]);
-          a.ks_out[cd] = make_uint2(L.key[i], L.sz[i]);
           const uint64_t so = sub_base + L.src[i];
           v4u rec;
-          rec.x = L.row[i];
-          rec.y = L.idx[i];
+          if constexpr (kPk) {
+            rec.x = L.key[i] | (L.sz[i] << a.pk_shift);
+            rec.y = L.row[i];
+          } else {
+            a.ks_out[cd] = make_uint2(L.key[i], L.sz[i]);
+            rec.x = L.row[i];
+            rec.y = L.idx[i];
+          }
           rec.z = (uint32_t)so;
           rec.w = (uint32_t)(so >> 32);
           gm((v4u*)a.rso_out)[cd] = rec;
@@ -1129,8 +1172,13 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
         const uint32_t i = (g + q) * kBlock + threadIdx.x;
         if (i < n) {
           const uint64_t cd = cdst[q];
-          a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
-          a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+          if constexpr (kPk) {
+            // a masked column keeps the size intact whatever the input holds
+            a.ks_out[cd] = make_uint2((L.key[i] & pk_mask) | (pz[q] << a.pk_shift), L.row[i]);
+          } else {
+            a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
+            a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
+          }
         }
         if (xfer_per_cell) {  // the sub-chunk spans source partitions (uniform)
           uint32_t key = 0;
@@ -1168,6 +1216,38 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
     settle<kFields>(cur, nxt);
     if constexpr (pass0 && !kVal) rpf = RowPf{settled(rpf_next.lo), settled(rpf_next.hi)};
   }
+}
+
+// One instance per kind of pass, so the loop has no branch between the two
+// load layouts: a branch there makes the compiler reconcile the registers of
+// in-flight loads at the join, which waits for them. The packed and wide
+// record forms are two loops of one kernel, chosen once per workgroup.
+// The records-only pass keeps no byte prefix and no byte cursors, and only a
+// bits-mode fan-out: under 53 KB of LDS and 168 VGPRs, so three workgroups fit
+// on a CU instead of two.
+// kVal (first pass only): every cell carries a value of its own (item vval)
+// in place of its row id, so no rows are expanded.
+template <bool kPass0, bool kDefer, bool kVal>
+__global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scatter(PassArgs a) {
+  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
+  __shared__ SortLdsT<kFan, !kDefer> L;
+  __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
+  __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
+  __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
+  __shared__ uint16_t s_ot[kPass0 ? kOwnerT + 1 : 1];   // their coarse owner table
+  __shared__ Seg s_seg;
+  __shared__ uint32_t s_si, s_extra;
+  __shared__ uint32_t s_red[kNW + 1];
+  if (aborted(a.abort_flag)) return;
+  if constexpr (!kVal && kPass0 != kDefer) {
+    if (packed_records(a.pk_on, a.no_pack)) {
+      scatter_body<kPass0, kDefer, kVal, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra,
+                                               s_red);
+      return;
+    }
+  }
+  scatter_body<kPass0, kDefer, kVal, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra,
+                                            s_red);
 }
 
 // (the 512-thread copy of this file needs only the records-only scatter)
@@ -1316,25 +1396,14 @@ __device__ void item_tails(const ItemDev& it, uint32_t i, const int32_t* item_st
 // kGather: the last pass moved records only; each cell's payload is read
 // from the previous level buffer at the bucket's src0 plus the cell's stored
 // offset. Otherwise payloads follow the records in the same level buffer.
-template <bool kGather>
-__global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
-  constexpr int kFields = kGather ? kFieldsRecSo : kFieldsRec;
+// kPk (gathering finish only): the last pass's records are packed (see
+// load_sub_pk16); no cell index travels, so no perm is written.
+template <bool kGather, bool kPk>
+__device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uint32_t* s_cc,
+                                            uint64_t* s_cb, uint32_t* s_red, uint64_t* s_red64) {
+  constexpr int kFields = kGather ? (kPk ? kFieldsPk16 : kFieldsRecSo) : kFieldsRec;
   const uint32_t* const so = kGather ? a.rso_in : nullptr;
-  __shared__ SortLds L;
-  __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
-  __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
-  __shared__ uint32_t s_red[kNW + 1];
-  __shared__ uint64_t s_red64[kNW + 1];
-  // Gathering finishes run their buckets in plain column order on all XCDs
-  // at once: the buckets in flight then read from one or two source segments
-  // (tens of MB, resident in the memory-side cache) instead of eight.
-  // Block i < n_items also writes item i's tails. This comes first: after an
-  // abort the bucket table below was never written, and only the status
-  // words are.
-  if (blockIdx.x < a.n_items)
-    item_tails(a.items[blockIdx.x], blockIdx.x, a.item_status, a.abort_flag, a.offset_width,
-               a.d_status, s_red64);
-  if (aborted(a.abort_flag)) return;
+  const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
   const uint64_t bk = kGather ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.g8);
   if (bk >= a.nbuckets) return;
   const Seg sg = a.buckets[bk];
@@ -1365,7 +1434,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       const uint32_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q) ks[q] = a.ks_in[sg.cell0 + min(c + q * kBlock, len - 1)];
+      for (int q = 0; q < kBatch; ++q) {
+        const uint64_t e = sg.cell0 + min(c + q * kBlock, len - 1);
+        if constexpr (kPk) {
+          const uint32_t x = gm(so)[4 * e];
+          ks[q] = make_uint2(x & pk_mask, x >> a.pk_shift);
+        } else {
+          ks[q] = a.ks_in[e];
+        }
+      }
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         const bool act = c + q * kBlock < len;
@@ -1402,7 +1479,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
   SubLoad cur, nxt;
   if (len) {
-    load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0, min((uint32_t)kSub, len));
+    if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0, min((uint32_t)kSub, len));
+    else load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0, min((uint32_t)kSub, len));
     settle<kFields>(cur, nxt);
   }
   for (uint32_t c0 = 0; c0 < len || (c0 == 0 && !multi); c0 += kSub) {
@@ -1412,7 +1490,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
-      key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
+      if constexpr (kPk) {
+        key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> a.pk_shift : 0u;
+        row[r] = cur.c[r]; idx[r] = 0u;
+      } else {
+        key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
+      }
       const uint32_t d = key[r] - sg.key_lo;
       dg[r] = i < n ? (d < nc ? d : nc - 1) : 0u;
     }
@@ -1429,7 +1512,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
       subtot = sub_src_prefix(sz, src, s_red);
     }
     // next sub-chunk's loads, issued after this one's registers were read
-    if (c1 < len) load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+    if (c1 < len) {
+      if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+    }
     sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
     if (!multi) {
       // one sub-chunk: its digit scan is the column layout of the whole bucket
@@ -1493,6 +1579,32 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
     settle<kFields>(cur, nxt);
     if (len == 0) break;
   }
+}
+
+template <bool kGather>
+__global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
+  __shared__ SortLds L;
+  __shared__ uint32_t s_cc[kFinishCols];  // per column: first output cell (bucket relative)
+  __shared__ uint64_t s_cb[kFinishCols];  // per column: first output byte (bucket relative)
+  __shared__ uint32_t s_red[kNW + 1];
+  __shared__ uint64_t s_red64[kNW + 1];
+  // Gathering finishes run their buckets in plain column order on all XCDs
+  // at once: the buckets in flight then read from one or two source segments
+  // (tens of MB, resident in the memory-side cache) instead of eight.
+  // Block i < n_items also writes item i's tails. This comes first: after an
+  // abort the bucket table below was never written, and only the status
+  // words are.
+  if (blockIdx.x < a.n_items)
+    item_tails(a.items[blockIdx.x], blockIdx.x, a.item_status, a.abort_flag, a.offset_width,
+               a.d_status, s_red64);
+  if (aborted(a.abort_flag)) return;
+  if constexpr (kGather) {
+    if (packed_records(a.pk_on, a.no_pack)) {
+      finish_body<kGather, true>(a, L, s_cc, s_cb, s_red, s_red64);
+      return;
+    }
+  }
+  finish_body<kGather, false>(a, L, s_cc, s_cb, s_red, s_red64);
 }
 
 // ----------------------------------------------------------------------------- children

@@ -543,6 +543,14 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   time_mark(p, s, "init");
 
   const int L = y.L;
+  // Packed records (see PassArgs): one matrix, one records-only pass, no perm,
+  // not a view operation, at most 28 column bits. The first histogram falls
+  // back to the wide records if any payload size does not fit beside them.
+  const int pk_shift =
+      n == 1 ? ceil_log2_u64((uint64_t)std::max<int64_t>(items[0].d.n_cols, 1)) : 32;
+  const int32_t pk_on = (n == 1 && L == 2 && !vc && items[0].dev.perm == nullptr &&
+                         pk_shift <= 28 && !env_cap("MGT_NO_PACK", 0, 1, 0)) ? 1 : 0;
+  int32_t* d_no_pack = d_abort + 4;  // in the uploaded (zeroed) abort block
   for (int l = 0; l < L; ++l) {
     PassArgs a{};
     a.items = d_items;
@@ -576,6 +584,9 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.offset_width = ow;
     a.has_val = (vc && l == 0) ? 1 : 0;
     a.allow_wide = n == 1 ? 1 : 0;
+    a.pk_on = pk_on;
+    a.pk_shift = pk_on ? pk_shift : 0;
+    a.no_pack = d_no_pack;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];
@@ -618,6 +629,9 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.d_status = d_status;
   f.offset_width = ow;
   f.g8 = align_up(y.nseg[L], 8);
+  f.pk_on = pk_on;
+  f.pk_shift = pk_on ? pk_shift : 0;
+  f.no_pack = d_no_pack;
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
 

@@ -32,15 +32,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int:
+def packs_records(a, perm: bool, n_passes: int) -> bool:
+    """Whether the library carries this single-matrix call's records packed:
+    one records-only pass, no perm, at most 28 column bits and every payload
+    size below 2^(32 - column bits) bytes."""
+    cb = max(int(a.n_cols) - 1, 0).bit_length()
+    if perm or n_passes != 2 or cb > 28:
+        return False
+    if a.nnz == 0:
+        return True
+    return int(np.diff(np.asarray(a.payload_off, dtype=np.int64)).max()) < (1 << (32 - cb))
+
+
+def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
+                 packed: bool = False) -> int:
     """Algorithmic bytes of one launch of a stage: each array it reads counted
     once and each array it writes counted once. Level-buffer records are 16
     bytes per cell (column, size, row, cell index); with two or more passes the
     last one moves records only and adds an 8-byte payload offset per cell,
-    which the finish reads to fetch each payload."""
+    which the finish reads to fetch each payload. Packed records (one
+    records-only pass, no perm) are 8 bytes after the first pass (column and
+    size in one word, row) and 16 after the second (plus the payload offset)."""
     nnz, P, o = a.nnz, a.payload_bytes, a.offset_width
     rec = nnz * 16
     deferred = n_passes >= 2
+    if packed:
+        if stage == "scatter" and pass_idx == 0:
+            return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + 8 * nnz + P
+        if stage == "scatter":
+            return 8 * nnz + 16 * nnz
+        if stage == "finish":
+            return 16 * nnz + P + 4 * nnz + (nnz + 1) * o + (a.n_cols + 1) * o + P
     if stage == "scatter" and pass_idx == 0:
         return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + rec + P
     if stage == "scatter" and deferred and pass_idx == n_passes - 1:
@@ -66,10 +88,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int) -> int
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "a7cd6210b0464ed60899f6ddc125e09fbf7301e51a481530f4d3eb0501877f84",
-                       "fetch_kib": 6534413.2, "write_kib": 17859884.3},
-    "k_finish": {"sources_sha256": "a7cd6210b0464ed60899f6ddc125e09fbf7301e51a481530f4d3eb0501877f84",
-                 "fetch_kib": 27581925, "write_kib": 18585075},
+    "k_pass_scatter": {"sources_sha256": "4fe3190cc8fb90d4ac302e810f8e01d2def81dce28042057c98deffb565f2cdf",
+                       "fetch_kib": 5328641.5, "write_kib": 12921723.7},
+    "k_finish": {"sources_sha256": "4fe3190cc8fb90d4ac302e810f8e01d2def81dce28042057c98deffb565f2cdf",
+                 "fetch_kib": 27657120, "write_kib": 18587447},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
@@ -627,6 +649,7 @@ def main():
     # average duration is
     per_kernel = {}
     n_passes = sum(1 for k in stages if k.rstrip("0123456789") == "scatter")
+    packed = packs_records(a, False, n_passes) and not os.environ.get("MGT_NO_PACK")
     for key, v in stages.items():
         st = key.rstrip("0123456789")
         if st not in ("scatter", "finish", "hist"):
@@ -634,7 +657,7 @@ def main():
         pidx = int(key[len(st):] or 0)
         e = per_kernel.setdefault(st, [0.0, 0, 0])
         e[0] += v
-        e[1] += kernel_bytes(a, st, pidx, False, n_passes)
+        e[1] += kernel_bytes(a, st, pidx, False, n_passes, packed)
         e[2] += 1
     dom_stage = max(per_kernel, key=lambda k: per_kernel[k][0])
     dom_ms = per_kernel[dom_stage][0] / per_kernel[dom_stage][2]

@@ -23,7 +23,13 @@ constexpr uint32_t kTileCells = 16384;    // cells per partition-pass tile (mult
 constexpr uint64_t kTargetTiles = 1024;   // tiles a single-matrix pass aims for
 constexpr uint64_t kTargetBuckets = 512;  // finish buckets a small single-matrix call aims for
 constexpr int kMaxBitsPerPass = kMaxPassBits;  // fan-out 256 per bits-mode pass
-constexpr uint32_t kMaxPartFanout = 512;  // preferred fan-out of the partition pass
+constexpr uint32_t kMaxPartFanout = 512;  // largest preferred fan-out of the partition pass
+// The partition pass aims for 256 digits (longer digit runs than 512) unless
+// its segments would then average more than this much payload: the gathering
+// finish streams a segment or two at a time through the 256 MB memory-side
+// cache (large matrix with 64 partitions: 256; heterogeneous matrix with 30 GB
+// of payload over 256 partitions: 512).
+constexpr uint64_t kSegPayloadTarget = 48ull << 20;
 constexpr int kMaxItems = 65535;
 static_assert(kTileCells % kSub == 0, "tile geometry");
 
@@ -84,8 +90,9 @@ int passes_for(int B, int first_cap, int mb) {
 // cells) on small matrices so that about kTargetBuckets workgroups share the
 // finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
 // parallelism.
-Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
-                    int mb, int mf, bool spread, int force_fb = -1) {
+Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
+                    const int64_t* bounds, bool partitioned, int mb, int mf, bool spread,
+                    int force_fb = -1) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -107,8 +114,10 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
     fb_ideal = mf;
   }
   fb_ideal = std::min(std::max(fb_ideal, 0), std::min(mf, K));
+  const uint32_t part_fan =
+      (uint64_t)std::max<int64_t>(payload_bytes, 0) / 256u > kSegPayloadTarget ? kMaxPartFanout : 256u;
   const int first_cap = partitioned
-      ? std::min(mb, R <= (int32_t)kMaxPartFanout ? floor_log2_u64(kMaxPartFanout / (uint32_t)R) : 0)
+      ? std::min(mb, R <= (int32_t)part_fan ? floor_log2_u64(part_fan / (uint32_t)R) : 0)
       : mb;
   // Fewest passes first, then the smallest finish width that achieves them.
   int best_fb = fb_ideal, best_L = 1 << 30;
@@ -136,13 +145,15 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bound
   return s;
 }
 
-Sched make_sched(int64_t n_cols, int64_t nnz, int32_t R, const int64_t* bounds, bool partitioned,
-                 bool spread, const Tune* t = nullptr) {
+Sched make_sched(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
+                 const int64_t* bounds, bool partitioned, bool spread, const Tune* t = nullptr) {
   const int mb = (t && t->pass_bits > 0) ? t->pass_bits : max_pass_bits();
   const int ff = (t && t->finish_bits >= 0) ? t->finish_bits : -1;
-  Sched s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, mb, max_finish_bits(), spread, ff);
+  Sched s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, mb, max_finish_bits(),
+                          spread, ff);
   if (s.n_levels > kMaxLevels)
-    s = make_sched_mb(n_cols, nnz, R, bounds, partitioned, kMaxBitsPerPass, kMaxFinishBits, spread);
+    s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, kMaxBitsPerPass,
+                      kMaxFinishBits, spread);
   return s;
 }
 
@@ -712,7 +723,8 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   HostItem& it = items[0];
   it.d = d;
   it.bounds = p->bounds.empty() ? nullptr : p->bounds.data();
-  it.s = make_sched(d.n_cols, d.nnz, d.n_parts, it.bounds, partitioned, true, &p->tune);
+  it.s = make_sched(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, it.bounds, partitioned, true,
+                    &p->tune);
   it.tile = p->tune.tile;
   if (!partitioned) it.d.n_parts = 1;
   fill_outputs(it.dev, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off, t_payload,
@@ -742,7 +754,8 @@ size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned, con
   items[0].d = d;
   if (!partitioned) items[0].d.n_parts = 1;
   items[0].bounds = bounds;
-  items[0].s = make_sched(d.n_cols, d.nnz, d.n_parts, bounds, partitioned, true, &t);
+  items[0].s =
+      make_sched(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, bounds, partitioned, true, &t);
   items[0].tile = t.tile;
   std::memset(&items[0].dev, 0, sizeof(ItemDev));
   return make_layout(items).bytes;
@@ -772,7 +785,8 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
     HostItem& it = items[(size_t)i];
     it.d = m.desc;
     it.bounds = m.desc.part_bounds;
-    it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.n_parts, m.desc.part_bounds, part, false);
+    it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.payload_bytes, m.desc.n_parts,
+                      m.desc.part_bounds, part, false);
     fill_outputs(it.dev, m.row_ptr, m.col, m.payload_off, m.payload, m.t_row_ptr, m.t_col,
                  m.t_payload_off, m.t_payload, m.perm);
     if (part) {
@@ -885,7 +899,7 @@ int mgt_view_plan(const mgt_desc* desc, int32_t op, int32_t in_view, mgt_plan_t*
   std::vector<HostItem> items(1);
   items[0].d = v;
   items[0].bounds = nullptr;
-  items[0].s = make_sched(v.n_cols, v.nnz, 1, nullptr, false, true);
+  items[0].s = make_sched(v.n_cols, v.nnz, v.payload_bytes, 1, nullptr, false, true);
   std::memset(&items[0].dev, 0, sizeof(ItemDev));
   p->ws_view = make_layout(items, (uint64_t)R + 1).bytes;
   *out = p;
@@ -908,7 +922,7 @@ int mgt_view_transform(mgt_plan_t p, const void* row_ptr, const int32_t* col,
   HostItem& it = items[0];
   it.d = v;
   it.bounds = nullptr;
-  it.s = make_sched(v.n_cols, v.nnz, 1, nullptr, false, true);
+  it.s = make_sched(v.n_cols, v.nnz, v.payload_bytes, 1, nullptr, false, true);
   fill_outputs(it.dev, row_ptr, col, payload_off, payload, o_row_ptr, o_col, o_payload_off,
                o_payload, perm);
   Layout y = make_layout(items, p->bounds.size());
@@ -1057,9 +1071,9 @@ int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bit
   t.tile = (uint32_t)tile_cells;
   const mgt_desc& d = plan->desc;
   for (int part = 0; part < 2; ++part) {  // a setting that needs over kMaxLevels passes is refused
-    const Sched s = make_sched_mb(d.n_cols, d.nnz, d.n_parts, plan->bounds.data(), part != 0,
-                                  pass_bits > 0 ? pass_bits : max_pass_bits(), max_finish_bits(),
-                                  true, finish_bits);
+    const Sched s = make_sched_mb(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, plan->bounds.data(),
+                                  part != 0, pass_bits > 0 ? pass_bits : max_pass_bits(),
+                                  max_finish_bits(), true, finish_bits);
     if (s.n_levels > kMaxLevels) return MGT_EUNSUPPORTED;
   }
   plan->tune = t;
@@ -1073,7 +1087,8 @@ int mgt_plan_schedule(mgt_plan_t plan, int32_t partitioned, int32_t* out) {
   if (!plan || !out || plan->batch || plan->view_op >= 0) return MGT_EINVAL;
   std::lock_guard<std::mutex> lock(plan->mu);
   const mgt_desc& d = plan->desc;
-  const Sched s = make_sched(d.n_cols, d.nnz, d.n_parts, plan->bounds.data(), partitioned != 0,
+  const Sched s = make_sched(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, plan->bounds.data(),
+                             partitioned != 0,
                              true, &plan->tune);  // as a call with these arguments makes it
   out[0] = s.n_levels;
   for (int l = 0; l < kMaxLevels; ++l) out[1 + l] = l < s.n_levels ? s.bits[l] : 0;

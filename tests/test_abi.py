@@ -271,12 +271,20 @@ def test_plan_schedule_settings():
     p = mgt.mgt_plan(1 << 23, 1 << 23, 1 << 29, 9663557316, 8, b)
     assert p.schedule() == {"passes": 2, "bits": [8, 8], "finish_bits": 7, "tile_cells": 16384,
                             "partition_pass": False}
-    assert p.schedule(True)["partition_pass"] and p.schedule(True)["bits"] == [3, 8]
+    # 64 partitions x 4: a fan-out of 256, whose segments hold 38 MB of payload on average
+    assert p.schedule(True)["partition_pass"] and p.schedule(True)["bits"] == [2, 8]
+    # 30 GB over 256 partitions: 256 segments would average 117 MB, so the
+    # partition pass takes a fan-out of 512 (256 x 2)
+    h = mgt.mgt_plan(1 << 21, 1 << 21, 1 << 30, 28 << 30, 8, [i * (1 << 13) for i in range(257)])
+    assert h.schedule(True) == {"passes": 2, "bits": [1, 8], "finish_bits": 4, "tile_cells": 16384,
+                                "partition_pass": True}
+    h2 = mgt.mgt_plan(1 << 21, 1 << 21, 1 << 30, 8 << 30, 8, [i * (1 << 13) for i in range(257)])
+    assert h2.schedule(True)["bits"][0] == 0  # 8 GB: 256 segments of 32 MB
     ws0 = p.workspace_bytes
     p.set_schedule(7, 9, 8192)
     assert p.schedule() == {"passes": 2, "bits": [7, 7], "finish_bits": 9, "tile_cells": 8192,
                             "partition_pass": False}
-    assert p.schedule(True)["bits"] == [3, 5]          # 17 column bits per partition: 3 + 5 + 9
+    assert p.schedule(True)["bits"] == [2, 6]          # 17 column bits per partition: 2 + 6 + 9
     with pytest.raises(mgt.MgtError) as e:            # 20 bits in passes of at most 4: five passes
         p.set_schedule(4, 3, 0)
     assert e.value.code == -5

@@ -50,14 +50,13 @@ struct PassArgs {
   int32_t allow_wide;         // a single-matrix call: its records-only pass may use the
                               // kWideBlock / kWideSub geometry (batches keep kBlock: their
                               // many small segments leave wide workgroups half empty)
-  // Packed records: a single matrix with exactly one records-only pass, called
-  // without perm and not as a view operation, keeps (column | size <<
-  // pk_shift, row) after the first pass and (column | size << pk_shift, row,
-  // payload offset) after the second, provided every payload size is below
-  // 2^(32 - pk_shift) bytes; the first histogram checks that and sets
-  // *no_pack otherwise.
+  // Packed records: a call with exactly one records-only pass, made without
+  // perm and not as a view operation, keeps (column | size << s, row) after
+  // the first pass and (column | size << s, row, payload offset) after the
+  // second, s being the item's column bits (ItemDev::pk_shift, <= 28),
+  // provided every payload size is below 2^(32 - s) bytes; the first
+  // histogram checks that and sets *no_pack otherwise.
   int32_t pk_on;
-  int32_t pk_shift;           // column bits, <= 28
   int32_t* no_pack;           // zero at the start of the call (uploaded with the status words)
 };
 
@@ -93,7 +92,6 @@ struct FinishArgs {
   int32_t offset_width;
   uint64_t g8;                // grid size (multiple of 8)
   int32_t pk_on;              // as in PassArgs
-  int32_t pk_shift;
   const int32_t* no_pack;
 };
 

@@ -434,7 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   uint64_t mybytes = 0;
   constexpr uint64_t kStride = (uint64_t)kBlock * kBatch;
   // sizes from 2^(32 - pk_shift) bytes on cannot be packed beside a column
-  const uint64_t pk_lim = 1ull << (32 - a.pk_shift);
+  const int pk_shift = it->pk_shift;
+  const uint64_t pk_lim = a.pk_on ? 1ull << (32 - pk_shift) : ~0ull;
   bool too_wide = false;
   if (a.pass == 0) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
@@ -489,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   } else {
     // pass 1 reads the first pass's records, packed or not (uniform)
     const bool pk = packed_records(a.pk_on, a.no_pack);
-    const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
+    const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
     for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
       const uint64_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
       for (int q = 0; q < kBatch; ++q) {
         const bool act = c + (uint64_t)q * kBlock < c_end;
         const uint32_t key = pk ? ks[q].x & pk_mask : ks[q].x;
-        const uint32_t sz = pk ? ks[q].x >> a.pk_shift : ks[q].y;
+        const uint32_t sz = pk ? ks[q].x >> pk_shift : ks[q].y;
         const uint32_t d = act ? digit_of(key, sg, s_lb, s_ot, osh, R) : 0u;
         hist_add_runs(act, d, sz, s_cnt, s_byt);
         if (act) mybytes += sz;
@@ -973,7 +974,6 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
                                              Seg& s_seg, uint32_t& s_si, uint32_t& s_extra,
                                              uint32_t* s_red) {
   constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;
-  const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
   {
@@ -1007,6 +1007,8 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   const uint64_t i_nrows = (uint64_t)it->n_rows;
   const uint8_t* const i_pay = it->payload;
   const int32_t i_fw = it->fixed_w;
+  const int pk_shift = it->pk_shift;  // packed records: column bits
+  const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
   const int lg = ow == 8 ? 3 : 2;  // (4-byte offsets keep every payload below 2^31 bytes)
   const uint64_t seg_out = sg.cell0;  // a segment's children share its cell range
 
@@ -1082,7 +1084,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
         if constexpr (kPk) {
-          key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> a.pk_shift : 0u;
+          key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> pk_shift : 0u;
           row[r] = cur.c[r]; idx[r] = 0u;
         } else {
           key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];
@@ -1126,7 +1128,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
           const uint64_t so = sub_base + L.src[i];
           v4u rec;
           if constexpr (kPk) {
-            rec.x = L.key[i] | (L.sz[i] << a.pk_shift);
+            rec.x = L.key[i] | (L.sz[i] << pk_shift);
             rec.y = L.row[i];
           } else {
             a.ks_out[cd] = make_uint2(L.key[i], L.sz[i]);
@@ -1174,7 +1176,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
           const uint64_t cd = cdst[q];
           if constexpr (kPk) {
             // a masked column keeps the size intact whatever the input holds
-            a.ks_out[cd] = make_uint2((L.key[i] & pk_mask) | (pz[q] << a.pk_shift), L.row[i]);
+            a.ks_out[cd] = make_uint2((L.key[i] & pk_mask) | (pz[q] << pk_shift), L.row[i]);
           } else {
             a.ks_out[cd] = make_uint2(L.key[i], pz[q]);
             a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
@@ -1403,11 +1405,12 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
                                             uint64_t* s_cb, uint32_t* s_red, uint64_t* s_red64) {
   constexpr int kFields = kGather ? (kPk ? kFieldsPk16 : kFieldsRecSo) : kFieldsRec;
   const uint32_t* const so = kGather ? a.rso_in : nullptr;
-  const uint32_t pk_mask = (uint32_t)((1ull << a.pk_shift) - 1u);
   const uint64_t bk = kGather ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.g8);
   if (bk >= a.nbuckets) return;
   const Seg sg = a.buckets[bk];
   const ItemDev* it = &a.items[sg.item];
+  const int pk_shift = it->pk_shift;  // packed records: column bits
+  const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
   const int ow = a.offset_width;
   const uint32_t nc = sg.key_hi - sg.key_lo;
   if (nc == 0) return;
@@ -1438,7 +1441,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
         const uint64_t e = sg.cell0 + min(c + q * kBlock, len - 1);
         if constexpr (kPk) {
           const uint32_t x = gm(so)[4 * e];
-          ks[q] = make_uint2(x & pk_mask, x >> a.pk_shift);
+          ks[q] = make_uint2(x & pk_mask, x >> pk_shift);
         } else {
           ks[q] = a.ks_in[e];
         }
@@ -1491,7 +1494,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
     for (int r = 0; r < kItems; ++r) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
       if constexpr (kPk) {
-        key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> a.pk_shift : 0u;
+        key[r] = cur.a[r] & pk_mask; sz[r] = i < n ? cur.a[r] >> pk_shift : 0u;
         row[r] = cur.c[r]; idx[r] = 0u;
       } else {
         key[r] = cur.a[r]; sz[r] = i < n ? cur.b[r] : 0u; row[r] = cur.c[r]; idx[r] = cur.d[r];

@@ -73,6 +73,8 @@ struct ItemDev {
   int32_t status_index;       // where this item's status word lives
   int32_t fixed_w;            // payload bytes of every cell when all cells have the same
                               // width (offset arrays unused), else -1
+  int32_t pk_shift;           // column bits of packed records, ceil(log2(n_cols)) (<= 28 when
+                              // the call packs)
 };
 
 // A contiguous cell range that covers the column interval [key_lo, key_hi).

@@ -433,6 +433,14 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   uint8_t* W = (uint8_t*)ws;
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
+  // Packed records (see PassArgs): one records-only pass, no perm, not a view
+  // operation, at most 28 column bits in every item. The first histogram
+  // falls back to the wide records if any payload size does not fit.
+  int32_t pk_on = (n >= 1 && y.L == 2 && !vc && !env_cap("MGT_NO_PACK", 0, 1, 0)) ? 1 : 0;
+  for (uint32_t i = 0; i < n && pk_on; ++i)
+    if (items[i].dev.perm != nullptr ||
+        ceil_log2_u64((uint64_t)std::max<int64_t>(items[i].d.n_cols, 1)) > 28)
+      pk_on = 0;
   // 1. upload items + bounds through the pinned staging buffer
   const size_t up_bytes = upload_bytes(y);
   if (!graph_staging) {
@@ -455,6 +463,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     d.key_bits = it.s.key_bits;
     d.part_mode = it.s.part_mode;
     d.status_index = (int32_t)i;
+    d.pk_shift = pk_on ? ceil_log2_u64((uint64_t)std::max<int64_t>(it.d.n_cols, 1)) : 0;
     d.fixed_w = (it.d.flags & MGT_FIXED_WIDTH)
                     ? (int32_t)(it.d.nnz > 0 ? it.d.payload_bytes / it.d.nnz : 0)
                     : -1;
@@ -554,13 +563,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   time_mark(p, s, "init");
 
   const int L = y.L;
-  // Packed records (see PassArgs): one matrix, one records-only pass, no perm,
-  // not a view operation, at most 28 column bits. The first histogram falls
-  // back to the wide records if any payload size does not fit beside them.
-  const int pk_shift =
-      n == 1 ? ceil_log2_u64((uint64_t)std::max<int64_t>(items[0].d.n_cols, 1)) : 32;
-  const int32_t pk_on = (n == 1 && L == 2 && !vc && items[0].dev.perm == nullptr &&
-                         pk_shift <= 28 && !env_cap("MGT_NO_PACK", 0, 1, 0)) ? 1 : 0;
   int32_t* d_no_pack = d_abort + 4;  // in the uploaded (zeroed) abort block
   for (int l = 0; l < L; ++l) {
     PassArgs a{};
@@ -596,7 +598,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.has_val = (vc && l == 0) ? 1 : 0;
     a.allow_wide = n == 1 ? 1 : 0;
     a.pk_on = pk_on;
-    a.pk_shift = pk_on ? pk_shift : 0;
     a.no_pack = d_no_pack;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
@@ -641,7 +642,6 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.offset_width = ow;
   f.g8 = align_up(y.nseg[L], 8);
   f.pk_on = pk_on;
-  f.pk_shift = pk_on ? pk_shift : 0;
   f.no_pack = d_no_pack;
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");

@@ -93,3 +93,28 @@ def test_batch_repeated_submits_reuse_plan_and_workspace():
                 assert torch.equal(o1[k], o2[k]), k
     ref = oracle.transpose(items[0])
     assert np.array_equal(outs2[0]["t_col"].cpu().numpy(), ref.t_col)
+
+
+@pytest.mark.parametrize("wide_cell", [False, True])
+def test_batch_packed_records(wide_cell, monkeypatch):
+    # a batch whose widest item needs two passes runs every item through one
+    # records-only pass; without perm its records are packed (per item column
+    # bits) unless some cell's payload does not fit beside its column
+    items = _mixed_items(13, 9)
+    items.append(gen.random_small(14, n_rows=60000, n_cols=1 << 21, deg_mean=5.0, w_lo=0, w_hi=11))
+    if wide_cell:  # 2^21 columns leave 11 bits: a 2,048-byte cell cannot be packed
+        a = items[3]
+        w = np.diff(a.payload_off).astype(np.int64)
+        w[len(w) // 2] = 2048
+        items[3] = from_arrays(a.n_rows, a.n_cols, a.row_ptr, a.col, w, None, 8, a.bounds, 3)
+    outs, st = _run_batch(items, perm=False)
+    assert (st == 0).all()
+    for a, h in zip(items, outs):
+        assert_matches_oracle(a, h, partitioned=a.n_parts > 1)
+    monkeypatch.setenv("MGT_NO_PACK", "1")
+    outs2, st2 = _run_batch(items, perm=False)
+    assert (st2 == 0).all()
+    for h, h2 in zip(outs, outs2):
+        for k, v in h.items():
+            if v is not None:
+                assert np.array_equal(v, h2[k]), k

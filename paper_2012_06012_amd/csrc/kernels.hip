@@ -549,7 +549,8 @@ constexpr int kFanBits = 1 << kMaxPassBits;  // fan-out of a bits-mode pass
 // round, counters per (digit, wave)), scans the counters digit-major and
 // stores the cells in sorted order. Registers hold kItems cells per lane in
 // wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
-template <class LT>
+// kIdx: the cell index travels (only perm needs it).
+template <bool kIdx = true, class LT>
 __device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t n,
                                          const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
                                          const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
@@ -597,7 +598,7 @@ __device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t 
       L.key[p] = key[r];
       L.sz[p] = sz[r];
       L.row[p] = row[r];
-      L.idx[p] = idx[r];
+      if constexpr (kIdx) L.idx[p] = idx[r];
       L.src[p] = src[r];
       L.dig[p] = (uint16_t)dg[r];
     }
@@ -1107,7 +1108,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
     }
-    sort_sub(L, F, dbits, n, key, dg, sz, row, idx, src);
+    sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
 
     const uint8_t* src_base = pass0 ? i_pay + sub_base : a.pay_in + sub_base;
     bool xfer_per_cell = false;
@@ -1519,7 +1520,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
       if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
       else load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
     }
-    sort_sub(L, nc, dbits, n, key, dg, sz, row, idx, src);
+    sort_sub<!kPk>(L, nc, dbits, n, key, dg, sz, row, idx, src);
     if (!multi) {
       // one sub-chunk: its digit scan is the column layout of the whole bucket
       for (uint32_t c = threadIdx.x; c < nc; c += kBlock)
@@ -1562,7 +1563,8 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
         const uint32_t i = (g + q) * kBlock + threadIdx.x;
         if (i < n) {
           gm(o_col)[pp[q]] = (int32_t)L.row[i];
-          if (o_perm) gm(o_perm)[pp[q]] = L.idx[i];
+          if constexpr (!kPk)  // packed records carry no cell index (no perm)
+            if (o_perm) gm(o_perm)[pp[q]] = L.idx[i];
           if (o_poff) st_off(o_poff, pp[q], (int64_t)pb[q], ow);
         }
       }

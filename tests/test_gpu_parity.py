@@ -20,6 +20,10 @@ def _both(a, partitioned_too=True):
     h, st = gpu_transpose(a, partitioned=False, perm=True)
     assert st == 0
     assert_matches_oracle(a, h)
+    # without perm: two-pass schedules carry packed records
+    h, st = gpu_transpose(a, partitioned=False, perm=False)
+    assert st == 0
+    assert_matches_oracle(a, h)
     if partitioned_too and a.n_rows == a.n_cols:
         h, st = gpu_transpose(a, partitioned=True, perm=True)
         assert st == 0

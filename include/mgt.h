@@ -118,6 +118,8 @@ int mgt_plan_destroy(mgt_plan_t plan);
  * payload / t_payload may be NULL when payload_bytes == 0; with
  * MGT_FIXED_WIDTH payload_off and t_payload_off may be NULL. Outputs must not
  * overlap inputs. workspace: >= the size mgt_plan reported, 256-byte aligned.
+ * A call without perm needs no cell index internally and may move less data
+ * (the outputs are the same either way).
  */
 int mgt_transpose(mgt_plan_t plan, const void* row_ptr, const int32_t* col,
                   const void* payload_off, const uint8_t* payload, void* t_row_ptr,

@@ -140,7 +140,9 @@ def measured_traffic(kname: str, args):
     return int((m["fetch_kib"] * COPY_SCALE["fetch"] + m["write_kib"] * COPY_SCALE["write"]) * 1024)
 
 
-def copy_calibration(mib: int):
+def copy_rate(mib: int, reps: int = 5) -> dict:
+    """A plain device-to-device copy of `mib` MiB, timed with events: the
+    achievable HBM rate (read plus write) on this part."""
     import torch
     n = mib << 20
     src = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
@@ -148,14 +150,19 @@ def copy_calibration(mib: int):
     dst.copy_(src)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 5
     ev0.record()
     for _ in range(reps):
         dst.copy_(src)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / reps
-    print(json.dumps({"copy_bytes_each_way": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_bytes_each_way": n, "ms": ms, "GBps_read_plus_write": 2 * n / ms / 1e6}
+
+
+def copy_calibration(mib: int):
+    print(json.dumps(copy_rate(mib)))
 
 
 def _device(a, dev, fixed_width=False):
@@ -668,6 +675,8 @@ def main():
 
     b_alg = a.algorithmic_bytes(partitioned=part)
     value = a.nnz / (ms * 1e-3)
+    # the achievable rate on this part, beside the 8 TB/s peak
+    copy_gbs = copy_rate(4096)["GBps_read_plus_write"]
     achieved_step = b_alg / (ms * 1e-3) / 1e9
 
     # bit-exactness on sampled output rows + global invariants
@@ -742,6 +751,8 @@ def main():
                    "n": a.n_rows, "nnz": a.nnz, "payload_bytes": a.payload_bytes,
                    "partitions": 64 if part else 1, "scale_shift": args.scale},
         "hbm_frac_step": achieved_step / HBM_PEAK_GBS,
+        "copy_GBps": copy_gbs,
+        "copy_frac_step": achieved_step / copy_gbs,
         "algorithmic_GBps_step": achieved_step,
         "algorithmic_bytes_step": b_alg,
         "bit_exact_sampled": exact,
@@ -749,6 +760,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": kname, "launches_per_step": dom_launches,
                      "achieved": dom_bytes / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": dom_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "frac_of_copy": dom_bytes / (dom_ms * 1e-3) / 1e9 / copy_gbs,
                      "traffic": traffic, "bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms},
         "cpu_baseline": cpu,
         "cpu_baseline_mt": cpu_mt,

@@ -161,3 +161,22 @@ def test_graph_replays_packed():
         assert int(status.cpu()[0]) == 0
         assert_matches_oracle(b, h)
     g.close()
+
+
+def test_validate_with_packed_records():
+    # validation stops a packed call on a bad column exactly as a wide one
+    from paper_2012_06012_amd import mgt
+    a = gen.random_small(31, n_rows=4000, n_cols=5000, deg_mean=5.0, w_lo=0, w_hi=9)
+    pb, fb = _two_pass(a, False)
+    d = to_device(a)
+    plan = mgt.plan_for(d, mgt.VALIDATE)
+    plan.set_schedule(pb, fb, 0)
+    out, st = mgt.transpose(d, plan=plan, validate=True)
+    assert int(st.cpu()[0]) == 0
+    assert_matches_oracle(a, host(out))
+    bad = d.col.clone()
+    bad[7] = a.n_cols + 3
+    d.col.copy_(bad)
+    out, st = mgt.transpose(d, plan=plan, validate=True)
+    torch.cuda.synchronize()
+    assert int(st.cpu()[0]) == mgt.ERANGE

@@ -67,6 +67,7 @@ def _check(a, partitioned, tile, monkeypatch):
     assert_matches_oracle(a, h3, partitioned=partitioned)
 
 
+
 @pytest.mark.parametrize("tile", [2048, 8192])  # 256-thread and 512-thread records-only pass
 @pytest.mark.parametrize("partitioned", [False, True])
 def test_large_recipe_two_passes(tile, partitioned, monkeypatch):
@@ -180,3 +181,23 @@ def test_validate_with_packed_records():
     out, st = mgt.transpose(d, plan=plan, validate=True)
     torch.cuda.synchronize()
     assert int(st.cpu()[0]) == mgt.ERANGE
+
+
+def test_hot_columns_packed(monkeypatch):
+    # two hot columns: buckets of over 12,000 cells (many sub-chunks) beside
+    # small ones, in one packed call
+    rng = np.random.default_rng(41)
+    n_rows, n_cols = 30000, 1 << 16
+    deg = rng.poisson(3.0, size=n_rows) + 1
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
+    hot = rng.random(nnz)
+    col[hot < 0.25] = 777
+    col[(hot >= 0.25) & (hot < 0.45)] = 40000
+    for i in range(n_rows):
+        col[rp[i]:rp[i + 1]].sort()
+    a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz), fill_seed=5)
+    assert (col == 777).sum() > 12288
+    _check(a, False, 0, monkeypatch)

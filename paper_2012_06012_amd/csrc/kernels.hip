@@ -436,6 +436,10 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   // sizes from 2^(32 - pk_shift) bytes on cannot be packed beside a column
   const int pk_shift = it->pk_shift;
   const uint64_t pk_lim = a.pk_on ? 1ull << (32 - pk_shift) : ~0ull;
+  const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
+  // a packed call's first pass reads (column | size << pk_shift) from here: the
+  // level buffer of (row, index) records that packed records leave unused
+  uint32_t* const pk4 = (a.pk_on && a.pass == 0) ? (uint32_t*)a.rk_out : nullptr;
   bool too_wide = false;
   if (a.pass == 0) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
@@ -463,6 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
           const bool act = c + (uint64_t)q * kBlock < c_end;
           const uint32_t d = act ? digit_of(key[q], sg, s_lb, s_ot, osh, R) : 0u;
           hist_add_runs(act, d, (uint32_t)fw, s_cnt, s_byt);
+          if (pk4 && act) pk4[sg.cell0 + c + (uint64_t)q * kBlock] = (key[q] & pk_mask) | ((uint32_t)fw << pk_shift);
         }
       }
     } else
@@ -484,13 +489,13 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
         const uint32_t d = act ? digit_of(key[q], sg, s_lb, s_ot, osh, R) : 0u;
         hist_add_runs(act, d, sz, s_cnt, s_byt);
         too_wide |= act && (uint64_t)sz >= pk_lim;
+        if (pk4 && act) pk4[sg.cell0 + c + (uint64_t)q * kBlock] = (key[q] & pk_mask) | (sz << pk_shift);
       }
     }
     if (a.pk_on && too_wide) gm(a.no_pack)[0] = 1;
   } else {
     // pass 1 reads the first pass's records, packed or not (uniform)
     const bool pk = packed_records(a.pk_on, a.no_pack);
-    const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
     for (uint64_t c0 = c_begin; c0 < c_end; c0 += kStride) {
       const uint64_t c = c0 + threadIdx.x;
       uint2 ks[kBatch];
@@ -950,6 +955,31 @@ __device__ __forceinline__ void load_sub_pk16(SubLoad& S, const uint32_t* rso, u
   }
 }
 constexpr int kFieldsPk8 = 1 | 4;
+// First pass of a packed call: (column | size << pk_shift) per cell, written
+// by the first histogram into the level buffer the first pass leaves unused
+// (indexed like the level buffers), and the payload offset of the sub-chunk's
+// first cell (item-local index kfirst) from the offsets or the fixed width.
+__device__ __forceinline__ void load_sub_pk4(SubLoad& S, const uint32_t* pk4, const void* poff,
+                                             uint64_t kfirst, uint64_t lfirst, uint32_t n, int lg,
+                                             int32_t fw) {
+  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const uint32_t i = w * kWaveCells + r * kWave + lane;
+    S.a[r] = gm(pk4)[lfirst + min(i, n - 1)];
+  }
+  S.pend = 0;
+  if (fw >= 0) {
+    const uint64_t b = kfirst * (uint64_t)fw;
+    S.base_lo = (uint32_t)b;
+    S.base_hi = (uint32_t)(b >> 32);
+  } else {
+    const uint8_t* b = (const uint8_t*)poff + (kfirst << lg);
+    S.base_lo = *gm((const uint32_t*)b);
+    S.base_hi = *gm((const uint32_t*)(b + (lg == 3 ? 4 : 0)));
+  }
+}
+constexpr int kFieldsPk4 = 1 | 32;
 constexpr int kFieldsPk16 = 1 | 4 | 16 | 64;
 
 // Payload sizes of a pass-0 sub-chunk from the low offset words: each cell's
@@ -998,7 +1028,9 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   constexpr bool pass0 = kPass0;
-  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : kFieldsPass0) : (kPk ? kFieldsPk8 : kFieldsRec);
+  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : (kPk ? kFieldsPk4 : kFieldsPass0))
+                                 : (kPk ? kFieldsPk8 : kFieldsRec);
+  const uint32_t* const pk4 = (const uint32_t*)a.rk_out;  // first pass of a packed call
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
   const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
   // item fields used in the loop, read once
@@ -1042,7 +1074,9 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw,
+    if constexpr (pass0 && kPk) load_sub_pk4(nxt, pk4, i_poff, kbase + c_begin, sg.cell0 + c_begin, n0, lg,
+                                             i_fw);
+    else if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw,
                                         kVal ? it->vval : nullptr);
     else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c_begin, n0);
     else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c_begin, n0);
@@ -1063,12 +1097,21 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
                              s_red);
         rpf_next = prefetch_row(i_rp, lg, i_nrows, r_next);  // next sub-chunk's rows
       }
-      sizes_from_offsets(cur, sz);
+      if constexpr (kPk) {
+#pragma unroll
+        for (int r = 0; r < kItems; ++r) {
+          const uint32_t i = w * kWaveCells + r * kWave + lane;
+          sz[r] = i < n ? cur.a[r] >> pk_shift : 0u;
+        }
+        sub_src_prefix(sz, src, s_red);  // offsets within the sub-chunk, from the sizes
+      } else {
+        sizes_from_offsets(cur, sz);
+      }
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
-        key[r] = cur.a[r];
-        src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
+        key[r] = kPk ? cur.a[r] & pk_mask : cur.a[r];
+        if constexpr (!kPk) src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
         if constexpr (kVal) row[r] = cur.d[r];
         else row[r] = i < n ? r0 + L.bpre[i] : 0u;
         idx[r] = (uint32_t)(kf + i);
@@ -1103,7 +1146,8 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
     // issuing these would wait for these too) and fly during the sort.
     if (c1 < c_end) {
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
+      if constexpr (pass0 && kPk) load_sub_pk4(nxt, pk4, i_poff, kbase + c1, sg.cell0 + c1, n1, lg, i_fw);
+      else if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
                                           kVal ? it->vval : nullptr);
       else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);

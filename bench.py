@@ -57,8 +57,12 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
     rec = nnz * 16
     deferred = n_passes >= 2
     if packed:
+        # the first histogram writes a 4-byte (column | size) word per cell,
+        # which the first pass reads instead of the columns and offsets
         if stage == "scatter" and pass_idx == 0:
-            return 4 * nnz + (nnz + 1) * o + (a.n_rows + 1) * o + P + 8 * nnz + P
+            return 4 * nnz + (a.n_rows + 1) * o + P + 8 * nnz + P
+        if stage == "hist" and pass_idx == 0:
+            return 4 * nnz + (nnz + 1) * o + 4 * nnz
         if stage == "scatter":
             return 8 * nnz + 16 * nnz
         if stage == "finish":

@@ -92,10 +92,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "a09b0a486b21879be89df452e5b0c6dd3c703b8f53cde13b295ca6ef4d4abd69",
-                       "fetch_kib": 5330360.3, "write_kib": 12919843.5},
-    "k_finish": {"sources_sha256": "a09b0a486b21879be89df452e5b0c6dd3c703b8f53cde13b295ca6ef4d4abd69",
-                 "fetch_kib": 27667640, "write_kib": 18587467},
+    "k_pass_scatter": {"sources_sha256": "147f5e8f54edfeba7f015387d14d34eac9161c178891c0993e34d4c151d0d60a",
+                       "fetch_kib": 4239101.8, "write_kib": 12921321.4},
+    "k_finish": {"sources_sha256": "147f5e8f54edfeba7f015387d14d34eac9161c178891c0993e34d4c151d0d60a",
+                 "fetch_kib": 27669564, "write_kib": 18587594},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

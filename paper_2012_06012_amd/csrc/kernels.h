@@ -58,6 +58,9 @@ struct PassArgs {
   // histogram checks that and sets *no_pack otherwise.
   int32_t pk_on;
   int32_t* no_pack;           // zero at the start of the call (uploaded with the status words)
+  int32_t pk_keys;            // with pk_on and no fixed-width item: the first histogram writes
+                              // (column | size << s) per cell into rk_out, which the first pass
+                              // reads instead of the columns and offsets
 };
 
 struct ChildArgs {

@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
   const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
   // a packed call's first pass reads (column | size << pk_shift) from here: the
   // level buffer of (row, index) records that packed records leave unused
-  uint32_t* const pk4 = (a.pk_on && a.pass == 0) ? (uint32_t*)a.rk_out : nullptr;
+  uint32_t* const pk4 = (a.pk_on && a.pk_keys && a.pass == 0) ? (uint32_t*)a.rk_out : nullptr;
   bool too_wide = false;
   if (a.pass == 0) {
     const uint64_t kbase = sg.cell0 - it->cell_base;
@@ -999,7 +999,7 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
 
 // kPk: packed records (see load_sub_pk8); only the first pass of a plain
 // (not view) call and the records-only pass have a packed form.
-template <bool kPass0, bool kDefer, bool kVal, bool kPk, class Lds>
+template <bool kPass0, bool kDefer, bool kVal, bool kPk, bool kKeys, class Lds>
 __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t* s_rc,
                                              uint64_t* s_rb, int32_t* s_lb, uint16_t* s_ot,
                                              Seg& s_seg, uint32_t& s_si, uint32_t& s_extra,
@@ -1028,7 +1028,8 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   const uint64_t c_begin = j * a.tile_cells;
   const uint64_t c_end = min((uint64_t)sg.len, c_begin + a.tile_cells);
   constexpr bool pass0 = kPass0;
-  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : (kPk ? kFieldsPk4 : kFieldsPass0))
+  constexpr bool kPk4 = kPass0 && kPk && kKeys;  // first pass reading the histogram's key words
+  constexpr int kFields = kPass0 ? (kVal ? kFieldsPass0 | 8 : (kPk4 ? kFieldsPk4 : kFieldsPass0))
                                  : (kPk ? kFieldsPk8 : kFieldsRec);
   const uint32_t* const pk4 = (const uint32_t*)a.rk_out;  // first pass of a packed call
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
@@ -1074,7 +1075,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   SubLoad cur, nxt;
   {
     const uint32_t n0 = (uint32_t)min((uint64_t)kSub, c_end - c_begin);
-    if constexpr (pass0 && kPk) load_sub_pk4(nxt, pk4, i_poff, kbase + c_begin, sg.cell0 + c_begin, n0, lg,
+    if constexpr (kPk4) load_sub_pk4(nxt, pk4, i_poff, kbase + c_begin, sg.cell0 + c_begin, n0, lg,
                                              i_fw);
     else if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c_begin, n0, lg, i_fw,
                                         kVal ? it->vval : nullptr);
@@ -1097,7 +1098,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
                              s_red);
         rpf_next = prefetch_row(i_rp, lg, i_nrows, r_next);  // next sub-chunk's rows
       }
-      if constexpr (kPk) {
+      if constexpr (kPk4) {
 #pragma unroll
         for (int r = 0; r < kItems; ++r) {
           const uint32_t i = w * kWaveCells + r * kWave + lane;
@@ -1111,7 +1112,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = w * kWaveCells + r * kWave + lane;
         key[r] = kPk ? cur.a[r] & pk_mask : cur.a[r];
-        if constexpr (!kPk) src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
+        if constexpr (!kPk4) src[r] = cur.c[r] - (uint32_t)sub_base;  // the sub-chunk spans under 2^32 bytes
         if constexpr (kVal) row[r] = cur.d[r];
         else row[r] = i < n ? r0 + L.bpre[i] : 0u;
         idx[r] = (uint32_t)(kf + i);
@@ -1146,7 +1147,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
     // issuing these would wait for these too) and fly during the sort.
     if (c1 < c_end) {
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if constexpr (pass0 && kPk) load_sub_pk4(nxt, pk4, i_poff, kbase + c1, sg.cell0 + c1, n1, lg, i_fw);
+      if constexpr (kPk4) load_sub_pk4(nxt, pk4, i_poff, kbase + c1, sg.cell0 + c1, n1, lg, i_fw);
       else if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
                                           kVal ? it->vval : nullptr);
       else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
@@ -1288,13 +1289,17 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   if (aborted(a.abort_flag)) return;
   if constexpr (!kVal && kPass0 != kDefer) {
     if (packed_records(a.pk_on, a.no_pack)) {
-      scatter_body<kPass0, kDefer, kVal, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra,
-                                               s_red);
+      if (kPass0 && a.pk_keys)
+        scatter_body<kPass0, kDefer, kVal, true, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                       s_extra, s_red);
+      else
+        scatter_body<kPass0, kDefer, kVal, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                        s_extra, s_red);
       return;
     }
   }
-  scatter_body<kPass0, kDefer, kVal, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra,
-                                            s_red);
+  scatter_body<kPass0, kDefer, kVal, false, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                   s_extra, s_red);
 }
 
 // (the 512-thread copy of this file needs only the records-only scatter)

@@ -564,6 +564,11 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
 
   const int L = y.L;
   int32_t* d_no_pack = d_abort + 4;  // in the uploaded (zeroed) abort block
+  // key words from the first histogram pay only where the first pass would
+  // otherwise read payload offsets (fixed-width items read columns only)
+  int32_t pk_keys = pk_on;
+  for (uint32_t i = 0; i < n && pk_keys; ++i)
+    if (items[i].d.flags & MGT_FIXED_WIDTH) pk_keys = 0;
   for (int l = 0; l < L; ++l) {
     PassArgs a{};
     a.items = d_items;
@@ -599,6 +604,7 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     a.allow_wide = n == 1 ? 1 : 0;
     a.pk_on = pk_on;
     a.no_pack = d_no_pack;
+    a.pk_keys = pk_keys;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];

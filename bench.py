@@ -92,10 +92,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
 MEASURED_TRAFFIC = {
     # both launches of a step averaged (the first pass moves payload, the last
     # one records only)
-    "k_pass_scatter": {"sources_sha256": "147f5e8f54edfeba7f015387d14d34eac9161c178891c0993e34d4c151d0d60a",
-                       "fetch_kib": 4239101.8, "write_kib": 12921321.4},
-    "k_finish": {"sources_sha256": "147f5e8f54edfeba7f015387d14d34eac9161c178891c0993e34d4c151d0d60a",
-                 "fetch_kib": 27669564, "write_kib": 18587594},
+    "k_pass_scatter": {"sources_sha256": "8170c0ec5bb70282bf86c86a58fe55f2576d0336707e8b55bdc9d3c172da75de",
+                       "fetch_kib": 4240824.3, "write_kib": 12920177.4},
+    "k_finish": {"sources_sha256": "8170c0ec5bb70282bf86c86a58fe55f2576d0336707e8b55bdc9d3c172da75de",
+                 "fetch_kib": 27679528, "write_kib": 18587633},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 

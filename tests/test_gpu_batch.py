@@ -118,3 +118,23 @@ def test_batch_packed_records(wide_cell, monkeypatch):
         for k, v in h.items():
             if v is not None:
                 assert np.array_equal(v, h2[k]), k
+
+
+def test_batch_packed_with_fixed_width_items():
+    # fixed-width items beside variable ones in one packed two-pass batch: the
+    # first pass then reads columns and offsets (or k * width) for every item
+    from paper_2012_06012_amd import mgt
+    items = _mixed_items(17, 5)
+    items.append(gen.random_small(18, n_rows=50000, n_cols=1 << 21, deg_mean=5.0, w_lo=0, w_hi=9))
+    fixed = [gen.random_small(19 + k, n_rows=3000, n_cols=3000, deg_mean=6.0, w_lo=w, w_hi=w)
+             for k, w in enumerate((12, 0, 28))]
+    mats = [to_device(a) for a in items] + [to_device(a, fixed_width=True) for a in fixed]
+    outs, status, plan, ws = mgt.batch_transpose(mats, perm=False)
+    torch.cuda.synchronize()
+    assert (status.cpu().numpy() == 0).all()
+    for a, o in zip(items + fixed, outs):
+        h = host(o)
+        if h.get("t_payload_off") is None:
+            w = a.payload_bytes // max(a.nnz, 1)
+            h = dict(h, t_payload_off=np.arange(a.nnz + 1, dtype=a.payload_off.dtype) * w)
+        assert_matches_oracle(a, h, partitioned=a.n_parts > 1)

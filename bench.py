@@ -572,6 +572,11 @@ def main():
     ap.add_argument("--fixed-width", action="store_true",
                     help="hetero: run the fixed-width mode (no payload offsets on the device)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): the library has no "
+              "multi-GPU exchange; partitions are logical partitions of one device.",
+              file=sys.stderr)
+        sys.exit(2)
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.mode == "batch":
@@ -586,10 +591,6 @@ def main():
         return bench_involution(args)
     if args.mode == "tune":
         return bench_tune(args)
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
-              "multi-GPU path; see DESIGN.md for how the transpose would shard.", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     from workloads import gen

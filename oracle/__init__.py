@@ -28,8 +28,6 @@ _MT_SRC = os.path.join(_HERE, "scantrans.c")
 _MT_LIB = os.path.join(_HERE, "libscantrans.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -5
-FAULT_NONE, FAULT_UNSTABLE, FAULT_SHORT_COPY, FAULT_INDEX_FOR_ROW, FAULT_SWAP_XFER, \
-    FAULT_INCLUSIVE_ROWPTR = range(6)
 
 
 def build(force: bool = True) -> str:
@@ -58,7 +56,6 @@ def _load():
             build(force=False)
         lib = ctypes.CDLL(_LIB)
         i64, i32, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
-        lib.mgo_set_fault.argtypes = [ctypes.c_int]
         lib.mgo_validate.argtypes = [i64, i64, i32, vp, vp, vp, i32, vp]
         lib.mgo_transpose.argtypes = [i64, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.mgo_partition_counts.argtypes = [i64, i64, i32, vp, vp, vp, i32, vp, vp, vp, vp,
@@ -104,32 +101,41 @@ class PartitionCounts:
     rdispls: np.ndarray      # [R, R]: [dst, src] receive displacement inside dst's receive buffer
 
 
-def set_fault(code: int) -> None:
-    """Plant one specific mistake in the oracle (tests of the pins only)."""
-    _load().mgo_set_fault(int(code))
-
-
 def validate(a, n_parts: int = 0) -> int:
     b = np.ascontiguousarray(a.bounds, dtype=np.int64) if n_parts else None
     return _load().mgo_validate(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col),
                                 _p(a.payload_off), n_parts, _p(b))
 
 
-def transpose(a) -> Transposed:
-    """Transpose of a workloads.Csr (plain definition, Gustavson counting sort)."""
+def alloc_transposed(a) -> Transposed:
+    """Output arrays for ``transpose(a, out=...)``, written once so their pages
+    are resident before a timed call."""
     dt = np.int32 if a.offset_width == 4 else np.int64
-    nnz = a.nnz
-    t_row_ptr = np.zeros(a.n_cols + 1, dtype=dt)
-    t_col = np.zeros(nnz, dtype=np.int32)
-    t_poff = np.zeros(nnz + 1, dtype=dt)
-    t_payload = np.zeros(a.payload_bytes, dtype=np.uint8)
-    perm = np.zeros(nnz, dtype=np.uint32)
+    t = Transposed(np.empty(a.n_cols + 1, dtype=dt), np.empty(a.nnz, dtype=np.int32),
+                   np.empty(a.nnz + 1, dtype=dt), np.empty(a.payload_bytes, dtype=np.uint8),
+                   np.empty(a.nnz, dtype=np.uint32))
+    for x in (t.t_row_ptr, t.t_col, t.t_payload_off, t.t_payload, t.perm):
+        x.fill(0)
+    return t
+
+
+def transpose(a, out: Optional[Transposed] = None) -> Transposed:
+    """Transpose of a workloads.Csr (plain definition, Gustavson counting sort).
+    ``out`` (from ``alloc_transposed``) receives the result when given."""
+    if out is None:
+        dt = np.int32 if a.offset_width == 4 else np.int64
+        nnz = a.nnz
+        out = Transposed(np.zeros(a.n_cols + 1, dtype=dt), np.zeros(nnz, dtype=np.int32),
+                         np.zeros(nnz + 1, dtype=dt), np.zeros(a.payload_bytes, dtype=np.uint8),
+                         np.zeros(nnz, dtype=np.uint32))
+    t_row_ptr, t_col, t_poff, t_payload, perm = (out.t_row_ptr, out.t_col, out.t_payload_off,
+                                                 out.t_payload, out.perm)
     st = _load().mgo_transpose(a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col),
                                _p(a.payload_off), _p(a.payload), _p(t_row_ptr), _p(t_col),
                                _p(t_poff), _p(t_payload), _p(perm))
     if st != OK:
         raise OracleError(st)
-    return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)
+    return out
 
 
 _mt_lib = None
@@ -209,4 +215,63 @@ def transpose_columns(a, c_lo: int, c_hi: int) -> Transposed:
     if st != OK:
         raise OracleError(st)
     t_poff[-1] = nbytes.value
+    return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)
+
+
+def transpose_sliced(a, slices: int = 16, threads: int = 0) -> Transposed:
+    """The whole transpose assembled from ``slices`` column ranges, each made
+    by the oracle's column-range mode (``mgo_transpose_columns``) in a thread
+    of its own; the same arrays as ``transpose``. Output row block
+    [c_lo, c_hi) of the transpose depends only on the input cells whose
+    column lies in it, so the slices are independent: each lands at the
+    cells and bytes of all earlier slices. For full-size checks on hosts with
+    many cores; pinned against ``transpose`` by the tests."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = _load()
+    n_cols, nnz = int(a.n_cols), int(a.nnz)
+    slices = max(1, min(int(slices), max(n_cols, 1)))
+    edges = [n_cols * s // slices for s in range(slices + 1)]
+    ranges = [(edges[s], edges[s + 1]) for s in range(slices)]
+    base = (a.n_rows, a.n_cols, a.offset_width, _p(a.row_ptr), _p(a.col), _p(a.payload_off),
+            _p(a.payload))
+    threads = threads or host_threads()
+
+    def size(r):
+        cells, nbytes = ctypes.c_int64(0), ctypes.c_int64(0)
+        st = lib.mgo_transpose_columns(*base, r[0], r[1], None, None, None, None, None,
+                                       ctypes.byref(cells), ctypes.byref(nbytes))
+        if st != OK:
+            raise OracleError(st)
+        return cells.value, nbytes.value
+
+    with ThreadPoolExecutor(threads) as ex:
+        sizes = list(ex.map(size, ranges))
+    cell0 = np.concatenate([[0], np.cumsum([c for c, _ in sizes])]).astype(np.int64)
+    byte0 = np.concatenate([[0], np.cumsum([b for _, b in sizes])]).astype(np.int64)
+    if int(cell0[-1]) != nnz:
+        raise OracleError(ERANGE)
+    dt = np.int32 if a.offset_width == 4 else np.int64
+    t_row_ptr = np.empty(n_cols + 1, dtype=dt)
+    t_col = np.empty(nnz, dtype=np.int32)
+    t_poff = np.empty(nnz + 1, dtype=dt)
+    t_payload = np.empty(int(byte0[-1]), dtype=np.uint8)
+    perm = np.empty(nnz, dtype=np.uint32)
+
+    def fill(s):
+        (lo, hi), c0, b0 = ranges[s], int(cell0[s]), int(byte0[s])
+        cells = int(cell0[s + 1]) - c0
+        rp = np.empty(hi - lo + 1, dtype=np.int64)
+        po = np.empty(cells, dtype=np.int64)
+        st = lib.mgo_transpose_columns(*base, lo, hi, _p(rp), _p(t_col[c0:c0 + cells]),
+                                       _p(po), _p(t_payload[b0:int(byte0[s + 1])]),
+                                       _p(perm[c0:c0 + cells]), None, None)
+        if st != OK:
+            raise OracleError(st)
+        t_row_ptr[lo:hi] = (rp[:-1] + c0).astype(dt)
+        t_poff[c0:c0 + cells] = (po + b0).astype(dt)
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(fill, range(slices)))
+    t_row_ptr[n_cols] = nnz
+    t_poff[nnz] = int(byte0[-1])
     return Transposed(t_row_ptr, t_col, t_poff, t_payload, perm)

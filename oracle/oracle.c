@@ -16,7 +16,7 @@
  *  - Multigraph cells: a row may hold several cells with the same column. They
  *    are kept, each with its own payload, in their original order (the output
  *    is ordered by column, then by original cell position; with canonical rows
- *    this is the paper's final "row-column ordering", Section 3 / Fig. 6).
+ *    this is the reorder of received cells that ends Section 3 / Fig. 6).
  *  - Section 2, sparse transpose step 1 and Section 3 rank intervals: rank
  *    (partition) r owns rows [bounds[r], bounds[r+1]) with 0-based ranks; as the
  *    matrix is square and the vertex set is unchanged by the transpose, the
@@ -41,11 +41,6 @@
 #include <string.h>
 
 #include "oracle.h"
-
-/* Test-only fault injection: tests set a nonzero code to plant one specific
- * mistake and check that the pins catch it. Zero (the default) is the oracle. */
-static int g_fault = 0;
-void mgo_set_fault(int code) { g_fault = code; }
 
 static int64_t ld_off(const void* a, int ow, int64_t i) {
   return ow == 4 ? (int64_t)((const int32_t*)a)[i] : ((const int64_t*)a)[i];
@@ -104,8 +99,6 @@ int mgo_transpose(int64_t n_rows, int64_t n_cols, int32_t ow, const void* row_pt
   for (int64_t k = 0; k < nnz; ++k) next[col[k] + 1] += 1;
   for (int64_t c = 0; c < n_cols; ++c) next[c + 1] += next[c];
   for (int64_t c = 0; c <= n_cols; ++c) st_off(t_row_ptr, ow, c, next[c]);
-  if (g_fault == MGO_FAULT_INCLUSIVE_ROWPTR)
-    for (int64_t c = 0; c < n_cols; ++c) st_off(t_row_ptr, ow, c, next[c + 1]);
 
   /* 2. visit rows in order, cells in order: cell k of row i goes to the next
    *    free slot of column col[k]; it becomes cell (col[k], i) of the transpose. */
@@ -114,21 +107,8 @@ int mgo_transpose(int64_t n_rows, int64_t n_cols, int32_t ow, const void* row_pt
   for (int64_t i = 0; i < n_rows; ++i) {
     for (int64_t k = ld_off(row_ptr, ow, i); k < ld_off(row_ptr, ow, i + 1); ++k) {
       int64_t p = next[col[k]]++;
-      t_col[p] = (int32_t)(g_fault == MGO_FAULT_INDEX_FOR_ROW ? k : i);
+      t_col[p] = (int32_t)i;
       p_of[p] = (uint32_t)k;
-    }
-  }
-  if (g_fault == MGO_FAULT_UNSTABLE) {
-    /* plant: reverse the order of the cells inside every column */
-    int64_t c0 = 0;
-    for (int64_t c = 0; c < n_cols; ++c) {
-      int64_t lo = c0, hi = ld_off(t_row_ptr, ow, c + 1) - 1;
-      c0 = hi + 1;
-      while (lo < hi) {
-        int32_t tc = t_col[lo]; t_col[lo] = t_col[hi]; t_col[hi] = tc;
-        uint32_t tp = p_of[lo]; p_of[lo] = p_of[hi]; p_of[hi] = tp;
-        ++lo; --hi;
-      }
     }
   }
 
@@ -138,11 +118,10 @@ int mgo_transpose(int64_t n_rows, int64_t n_cols, int32_t ow, const void* row_pt
   for (int64_t p = 0; p < nnz; ++p) {
     const int64_t k = p_of[p];
     const int64_t src = ld_off(payload_off, ow, k);
-    int64_t sz = ld_off(payload_off, ow, k + 1) - src;
+    const int64_t sz = ld_off(payload_off, ow, k + 1) - src;
     st_off(t_payload_off, ow, p, acc);
-    if (g_fault == MGO_FAULT_SHORT_COPY && sz > 0) sz -= 1;
     if (sz > 0) memcpy(t_payload + acc, payload + src, (size_t)sz);
-    acc += ld_off(payload_off, ow, k + 1) - src;
+    acc += sz;
   }
   st_off(t_payload_off, ow, nnz, acc);
   if (perm) for (int64_t p = 0; p < nnz; ++p) perm[p] = p_of[p];
@@ -168,13 +147,8 @@ int mgo_partition_counts(int64_t n_rows, int64_t n_cols, int32_t ow, const void*
     for (int64_t k = ld_off(row_ptr, ow, i); k < ld_off(row_ptr, ow, i + 1); ++k) {
       const int32_t dst = owner(bounds, R, col[k]);
       const int64_t sz = ld_off(payload_off, ow, k + 1) - ld_off(payload_off, ow, k);
-      if (g_fault == MGO_FAULT_SWAP_XFER) {
-        xfer_cells[(int64_t)dst * R + src] += 1;
-        xfer_bytes[(int64_t)dst * R + src] += sz;
-      } else {
-        xfer_cells[(int64_t)src * R + dst] += 1;
-        xfer_bytes[(int64_t)src * R + dst] += sz;
-      }
+      xfer_cells[(int64_t)src * R + dst] += 1;
+      xfer_bytes[(int64_t)src * R + dst] += sz;
     }
   }
   /* Output partition s holds every cell received by rank s: its offset is the

@@ -12,17 +12,6 @@ extern "C" {
 
 enum { MGO_OK = 0, MGO_EINVAL = -1, MGO_ERANGE = -2, MGO_ENOMEM = -3, MGO_EUNSUPPORTED = -5 };
 
-/* Test-only planted mistakes (mgo_set_fault); 0 = none. */
-enum {
-  MGO_FAULT_NONE = 0,
-  MGO_FAULT_UNSTABLE = 1,          /* equal-column cells in reverse order     */
-  MGO_FAULT_SHORT_COPY = 2,        /* last payload byte of every cell dropped */
-  MGO_FAULT_INDEX_FOR_ROW = 3,     /* cell index written where the row goes   */
-  MGO_FAULT_SWAP_XFER = 4,         /* X and B built transposed                */
-  MGO_FAULT_INCLUSIVE_ROWPTR = 5   /* inclusive instead of exclusive offsets  */
-};
-void mgo_set_fault(int code);
-
 /* ow = offset width in bytes (4 or 8) of row_ptr / payload_off / outputs. */
 int mgo_validate(int64_t n_rows, int64_t n_cols, int32_t ow, const void* row_ptr,
                  const int32_t* col, const void* payload_off, int32_t R, const int64_t* bounds);

@@ -73,7 +73,7 @@ def run(a):
             blocks_v.extend(send_vals[r][lo:hi])
         m = np.concatenate(blocks_m) if blocks_m else np.zeros((0, 4), np.int64)
         assert len(m) == recv_counts[s].sum()
-        # step 6: row-column ordering of the received data
+        # step 6: the receiver orders what it got by column, then row (Fig. 6)
         order = np.argsort(m[:, 1], kind="stable")
         out_meta.append(m[order])
         out_vals.extend(blocks_v[i] for i in order)

@@ -725,6 +725,9 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   if (st != MGT_OK) return st;
   if (partitioned && (!xc || !xb || !pco || !pbo)) return MGT_EINVAL;
   if (!ws || ((uintptr_t)ws & 255u)) return MGT_EINVAL;
+  // The schedule is read under the plan's lock (mgt_plan_set_schedule may
+  // change it from another thread) and the lock is held through the launches.
+  std::lock_guard<std::mutex> lock(p->mu);
   std::vector<HostItem> items(1);
   HostItem& it = items[0];
   it.d = d;
@@ -746,11 +749,7 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   if (!partitioned) it.bounds = nullptr;
   Layout y = make_layout(items);
   if (ws_bytes < y.bytes) return MGT_ENOMEM;
-  if (graph) {
-    std::lock_guard<std::mutex> lock(p->mu);
-    return record_graph(p, items, y, ws, d_status, graph);
-  }
-  std::lock_guard<std::mutex> lock(p->mu);
+  if (graph) return record_graph(p, items, y, ws, d_status, graph);
   p->timing.used = 0;
   return run(p, items, y, ws, d_status, s);
 }

@@ -416,11 +416,14 @@ def workspace_for(plan: Plan, device) -> torch.Tensor:
 
 
 def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: bool = False,
-              partitioned: bool = False, validate: bool = False, stream=None, out=None):
+              partitioned: bool = False, validate: bool = False, stream=None, out=None,
+              status=None):
     """Allocates outputs and runs mgt_transpose / mgt_transpose_partitioned.
 
     Returns (outputs dict, status tensor). Asynchronous: read the tensors after
-    synchronising the stream.
+    synchronising the stream. `status` (one int32 on the device) may be passed
+    to reuse it; otherwise one is taken from torch's allocator uninitialised
+    (the library writes it on every call it launches, so no fill kernel runs).
     """
     flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
     if plan is None:
@@ -430,7 +433,8 @@ def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: b
         workspace = workspace_for(plan, dev)
     if out is None:
         out = alloc_outputs(a, perm, partitioned, dev)
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
     if partitioned:
         mgt_transpose_partitioned(plan, a.row_ptr, a.col, a.payload_off, a.payload,
                                   out["t_row_ptr"], out["t_col"], out["t_payload_off"],

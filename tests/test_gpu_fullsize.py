@@ -1,16 +1,22 @@
-"""GPU parity at the full sizes of the benchmark workloads, on the launch
-configuration bench.py times (default plan, one call), checked on outputs the
-oracle can produce piece by piece:
+"""GPU parity at the full sizes of the benchmark workloads, element by element.
 
-* every column's degree (the transposed row offsets) against a bincount of the
-  input columns (torch's, on the device);
-* complete transposed rows (ids, payload offsets relative to the row, payload
-  bytes) for sampled column ranges, including the first and the last, from
-  the oracle's column-range mode;
-* for the partitioned form, the partition offsets against the transposed row
-  offsets at the bounds, and the transfer-matrix sums against the cells per
-  source and destination partition.
+Each test builds the whole workload on the host, runs the oracle once over the
+whole matrix (``oracle.transpose_sliced``: the oracle's column-range mode over
+disjoint column ranges in host threads, pinned against ``oracle.transpose``;
+and ``oracle.partition_counts``), then runs
+the library in the launch configurations the benchmarks time and compares
+every output array in full: the transposed row offsets, column ids, payload
+offsets and payload bytes, the cell permutation where one is emitted, and for
+the partitioned form the transfer matrices, partition offsets and both
+displacement matrices (paper Section 2: M^T_ij = M_ji with repeated cells in
+input order; Section 3: the receiver's ordering by column, then row).
+
+The large multigraph (2^29 cells) carries 9.66 GB of payload and the
+heterogeneous one (2^30 cells) 30 GB, so payload offsets above 2^32 (the
+high word of the records' offsets) are compared in full here.
 """
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -18,59 +24,125 @@ import torch
 import oracle
 from workloads import gen
 
-from .common import to_device
+from .common import first_mismatch, to_device
 
 pytestmark = pytest.mark.gpu
 
-
-def _sampled_parity(a, d, out, ranges):
-    deg = torch.bincount(d.col.long(), minlength=a.n_cols)
-    assert torch.equal(torch.diff(out["t_row_ptr"].long()), deg)
-    t_row_ptr = out["t_row_ptr"].cpu().numpy()
-    assert int(t_row_ptr[-1]) == a.nnz
-    for lo, hi in ranges:
-        s = oracle.transpose_columns(a, lo, hi)
-        p0, p1 = int(t_row_ptr[lo]), int(t_row_ptr[hi])
-        assert np.array_equal(t_row_ptr[lo:hi + 1] - p0, s.t_row_ptr)
-        assert np.array_equal(out["t_col"][p0:p1].cpu().numpy(), s.t_col)
-        po = out["t_payload_off"][p0:p1 + 1].cpu().numpy()
-        assert np.array_equal(po - po[0], s.t_payload_off)
-        assert np.array_equal(out["t_payload"][int(po[0]):int(po[-1])].cpu().numpy(), s.t_payload)
-    return t_row_ptr
+_PART_KEYS = ("xfer_cells", "xfer_bytes", "part_cell_off", "part_byte_off", "sdispls", "rdispls")
 
 
-def _ranges(n, width, seed):
-    rng = np.random.default_rng(seed)
-    return [(0, width), (n - width, n)] + [(int(c), int(c) + width)
-                                           for c in rng.integers(0, n - width, size=3)]
+def _log(msg):
+    print(msg, flush=True)
 
 
-def test_large_plain_full_size():
-    from paper_2012_06012_amd import mgt
-    a = gen.large(seed=0)                      # 2^23 x 2^23, 2^29 cells
-    d = to_device(a)
-    out, status = mgt.transpose(d)
+def compare_full(out: dict, ref, pc=None, what: str = ""):
+    """Every output array against the oracle's; arrays come to the host one at
+    a time."""
     torch.cuda.synchronize()
-    assert int(status.cpu()[0]) == 0
-    _sampled_parity(a, d, out, _ranges(a.n_cols, 48, 1))
-    del d, out
+    for k in ("t_row_ptr", "t_col", "t_payload_off", "t_payload", "perm"):
+        t = out.get(k)
+        if t is None:
+            continue
+        h = t.cpu().numpy()
+        r = getattr(ref, k)
+        if k == "perm":
+            h = h.view(np.uint32)
+        assert h.shape == r.shape and np.array_equal(h, r), (what, k, first_mismatch(h, r))
+        del h
+    if pc is not None:
+        for k in _PART_KEYS:
+            if out.get(k) is None:
+                continue
+            h = out[k].cpu().numpy()
+            assert np.array_equal(h, getattr(pc, k)), (what, k)
+    gc.collect()
+
+
+def _run(d, *, partitioned, perm, what):
+    from paper_2012_06012_amd import mgt
+    _log(f"[fullsize] {what}: transpose")
+    out, status = mgt.transpose(d, perm=perm, partitioned=partitioned)
+    torch.cuda.synchronize()
+    assert int(status.cpu()[0]) == mgt.OK, what
+    return out
+
+
+def test_large_full_size():
+    """Large multigraph (2^23 x 2^23, 2^29 cells, int64 offsets): the plain
+    call the headline bench times (packed records, no perm), then the
+    partitioned call with R = 64 and perm (wide records)."""
+    a = gen.large(seed=0)
+    _log(f"[fullsize] large: {a.nnz} cells, {a.payload_bytes} payload bytes")
+    ref = oracle.transpose_sliced(a, slices=2 * oracle.host_threads())
+    pc = oracle.partition_counts(a)
+    d = to_device(a)
+    out = _run(d, partitioned=False, perm=False, what="large plain")
+    compare_full(out, ref, what="large plain")
+    del out
+    torch.cuda.empty_cache()
+    out = _run(d, partitioned=True, perm=True, what="large partitioned R=64, perm")
+    compare_full(out, ref, pc, what="large partitioned")
+    del out, d, ref, pc, a
+    gc.collect()
     torch.cuda.empty_cache()
 
 
-def test_hetero_partitioned_full_size():
-    from paper_2012_06012_amd import mgt
-    a = gen.hetero(seed=0)                     # 2^21 x 2^21, 2^30 cells, R = 256
+def test_hetero_full_size():
+    """Heterogeneous multigraph (2^21 x 2^21, 2^30 cells, 28-byte payload,
+    R = 256): the partitioned call of its bench mode, then the fixed-width
+    form (no payload offsets read on the device)."""
+    a = gen.hetero(seed=0)
+    _log(f"[fullsize] hetero: {a.nnz} cells, {a.payload_bytes} payload bytes")
+    ref = oracle.transpose_sliced(a, slices=2 * oracle.host_threads())
+    pc = oracle.partition_counts(a)
+    ref.perm = None  # neither call below emits perm; frees 4 GB
     d = to_device(a)
+    out = _run(d, partitioned=True, perm=False, what="hetero partitioned")
+    compare_full(out, ref, pc, what="hetero partitioned")
+    del out, d
+    gc.collect()
+    torch.cuda.empty_cache()
+    from paper_2012_06012_amd import mgt
+    d = to_device(a, fixed_width=True)
+    _log("[fullsize] hetero fixed-width partitioned: transpose")
     out, status = mgt.transpose(d, partitioned=True)
     torch.cuda.synchronize()
-    assert int(status.cpu()[0]) == 0
-    t_row_ptr = _sampled_parity(a, d, out, _ranges(a.n_cols, 16, 2)[:4])
-    b = np.asarray(a.bounds, np.int64)
-    assert np.array_equal(out["part_cell_off"].cpu().numpy(), t_row_ptr[b])
-    x = out["xfer_cells"].cpu().numpy()
-    rows_per_part = np.diff(np.asarray(a.row_ptr, np.int64)[b])
-    assert np.array_equal(x.sum(axis=1), rows_per_part)       # cells each source sends
-    assert np.array_equal(x.sum(axis=0), np.diff(t_row_ptr[b]))  # cells each destination gets
-    assert int(out["xfer_bytes"].cpu().numpy().sum()) == a.payload_bytes
-    del d, out
+    assert int(status.cpu()[0]) == mgt.OK
+    compare_full(out, ref, pc, what="hetero fixed-width")
+    del out, d, ref, pc, a
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def test_payload_offsets_above_4g():
+    """A mid-size matrix whose payload offsets cross 2^32 (2^20 x 2^20,
+    about 8.4e7 cells of 48-80 bytes, 5.4 GB of payload), compared in full
+    in every record form: packed (no perm), wide (perm), partitioned, and a
+    forced three-pass schedule whose middle pass moves payload too."""
+    from paper_2012_06012_amd import mgt
+    n = 1 << 20
+    a = gen.generate(n, n, seed=17, deg_law=gen.DEG_POISSON, deg_mean=80.0,
+                     pay_law=gen.PAY_BYTES, w_lo=48, w_hi=80, offset_width=8,
+                     bounds=gen.equal_bounds(n, 16))
+    assert a.payload_bytes > 2**32 + 2**30, a.payload_bytes
+    _log(f"[fullsize] >4G: {a.nnz} cells, {a.payload_bytes} payload bytes")
+    ref = oracle.transpose_sliced(a, slices=2 * oracle.host_threads())
+    pc = oracle.partition_counts(a)
+    d = to_device(a)
+    for perm, part in ((False, False), (True, False), (False, True)):
+        what = f">4G perm={perm} partitioned={part}"
+        out = _run(d, partitioned=part, perm=perm, what=what)
+        compare_full(out, ref, pc if part else None, what=what)
+        del out
+        torch.cuda.empty_cache()
+    plan = mgt.plan_for(d, 0)
+    plan.set_schedule(6, 6, 0)  # 20 column bits: 14 over three passes, 6 in the finish
+    assert plan.schedule()["passes"] == 3, plan.schedule()
+    _log("[fullsize] >4G three passes: transpose")
+    out, status = mgt.transpose(d, plan=plan)
+    torch.cuda.synchronize()
+    assert int(status.cpu()[0]) == mgt.OK
+    compare_full(out, ref, what=">4G three passes")
+    del out, d, ref, pc, a
+    gc.collect()
     torch.cuda.empty_cache()

@@ -98,6 +98,8 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
     call (template arguments as the library instantiates them)."""
     if stage == "hist":
         return "mgt::geo256::k_pass_hist"
+    if stage == "finishb":
+        return "mgt::geo256::k_finish_bucket"
     if stage == "finish":
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
@@ -745,13 +747,18 @@ def main():
     kernels = {}
     for key, v in stages.items():
         st = key.rstrip("0123456789")
-        if st not in ("scatter", "finish", "hist"):
+        if st not in ("scatter", "finish", "finishb", "hist"):
             continue
         pidx = int(key[len(st):] or 0)
         name = profiler_kernel_name(st, pidx, n_passes, part)
         e = kernels.setdefault(name, [0.0, 0, 0])
         e[0] += v
-        e[1] += kernel_bytes(a, st, pidx, False, n_passes, packed)
+        # with the whole-bucket finish, k_finish only takes the buckets it left
+        # (none on this workload) and writes the tails
+        bytes_st = "finish" if st == "finishb" else st
+        if st == "finish" and "finishb0" in stages:
+            bytes_st = "tails"
+        e[1] += kernel_bytes(a, bytes_st, pidx, False, n_passes, packed)
         e[2] += 1
     dom = max(kernels, key=lambda k: kernels[k][0])
     dom_ms = kernels[dom][0] / kernels[dom][2]

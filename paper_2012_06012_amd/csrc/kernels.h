@@ -96,6 +96,10 @@ struct FinishArgs {
   uint64_t g8;                // grid size (multiple of 8)
   int32_t pk_on;              // as in PassArgs
   const int32_t* no_pack;
+  uint8_t* bucket_done;       // [nbuckets] gathering finish with packed records: 1 where
+                              // k_finish_bucket wrote the bucket (k_finish skips it), else 0;
+                              // null: k_finish takes every bucket
+  uint32_t grid;              // k_finish_bucket: workgroups (one per CU)
 };
 
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
@@ -130,6 +134,9 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s);  // records-only pass
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+// Whole-bucket finish of a gathering call with packed records (runs before
+// launch_finish, which then skips the buckets it wrote).
+hipError_t launch_finish_bucket(const FinishArgs& a, hipStream_t s);
 // Scratch needed by launch_scan for n_max elements (bytes).
 inline uint64_t scan_scratch_bytes(uint64_t n_max) {
   return 2 * 8 * ((n_max + kScanBlock - 1) / kScanBlock + 1) + 64;

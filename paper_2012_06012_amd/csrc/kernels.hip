@@ -759,23 +759,26 @@ constexpr int kPay = 4;  // cells per lane whose payload words are held at once
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte aligned record
 typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
-struct PayRegs {
-  u32x4a v[kPay][2];
+template <int N>
+struct PayRegsT {
+  u32x4a v[N][2];
   bool fast;
 };
+using PayRegs = PayRegsT<kPay>;
 
-__device__ __forceinline__ void pay_load(PayRegs& P, uint8_t* const (&dst)[kPay],
-                                         const uint8_t* const (&src)[kPay],
-                                         const uint32_t (&sz)[kPay]) {
+template <int N>
+__device__ __forceinline__ void pay_load(PayRegsT<N>& P, uint8_t* const (&dst)[N],
+                                         const uint8_t* const (&src)[N],
+                                         const uint32_t (&sz)[N]) {
   bool fast = true;
 #pragma unroll
-  for (int r = 0; r < kPay; ++r)
+  for (int r = 0; r < N; ++r)
     fast &= sz[r] == 0u ||
             (sz[r] <= 32u && ((sz[r] | (uint32_t)(uintptr_t)src[r] | (uint32_t)(uintptr_t)dst[r]) & 3u) == 0);
   P.fast = fast;
   if (fast) {
 #pragma unroll
-    for (int r = 0; r < kPay; ++r) {
+    for (int r = 0; r < N; ++r) {
       const GMEM uint8_t* s = gm(src[r]);
       const uint32_t z = sz[r];
       if (z >= 16u) P.v[r][0] = *(const GMEM u32x4a*)s;
@@ -790,12 +793,13 @@ __device__ __forceinline__ void pay_load(PayRegs& P, uint8_t* const (&dst)[kPay]
   }
 }
 
-__device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst)[kPay],
-                                          const uint8_t* const (&src)[kPay],
-                                          const uint32_t (&sz)[kPay]) {
+template <int N>
+__device__ __forceinline__ void pay_store(const PayRegsT<N>& P, uint8_t* const (&dst)[N],
+                                          const uint8_t* const (&src)[N],
+                                          const uint32_t (&sz)[N]) {
   if (P.fast) {
 #pragma unroll
-    for (int r = 0; r < kPay; ++r) {
+    for (int r = 0; r < N; ++r) {
       GMEM uint8_t* d = gm(dst[r]);
       const uint32_t z = sz[r];
       if (z >= 16u) *(GMEM u32x4a*)d = P.v[r][0];
@@ -810,21 +814,21 @@ __device__ __forceinline__ void pay_store(const PayRegs& P, uint8_t* const (&dst
   } else {
     bool small = true;
 #pragma unroll
-    for (int r = 0; r < kPay; ++r) small &= sz[r] <= 16u;
+    for (int r = 0; r < N; ++r) small &= sz[r] <= 16u;
     if (small) {
-      uint8_t v[kPay][16];
+      uint8_t v[N][16];
 #pragma unroll
-      for (int r = 0; r < kPay; ++r)
+      for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int j = 0; j < 16; ++j)
           if ((uint32_t)j < sz[r]) v[r][j] = gm(src[r])[j];
 #pragma unroll
-      for (int r = 0; r < kPay; ++r)
+      for (int r = 0; r < N; ++r)
 #pragma unroll
         for (int j = 0; j < 16; ++j)
           if ((uint32_t)j < sz[r]) gm(dst[r])[j] = v[r][j];
     } else {
-      for (int r = 0; r < kPay; ++r)
+      for (int r = 0; r < N; ++r)
         if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
     }
   }
@@ -1654,11 +1658,273 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
   if (aborted(a.abort_flag)) return;
   if constexpr (kGather) {
     if (packed_records(a.pk_on, a.no_pack)) {
+      // buckets k_finish_bucket wrote are done
+      if (a.bucket_done && blockIdx.x < a.nbuckets && a.bucket_done[blockIdx.x]) return;
       finish_body<kGather, true>(a, L, s_cc, s_cb, s_red, s_red64);
       return;
     }
   }
   finish_body<kGather, false>(a, L, s_cc, s_cb, s_red, s_red64);
+}
+
+// ----------------------------------------------------------------------------- whole-bucket finish
+
+// A gathering finish with packed records (two passes, no perm) sorts a bucket
+// of up to kBkCap cells in one piece: its records are read once, ranked by
+// column with a ballot multisplit (each wave holds a contiguous run of
+// kBkWaveCells cells, so wave order is cell order and the ranks are stable),
+// placed in LDS in output order, and written out in that order. Consecutive
+// output cells then go to consecutive addresses of t_col, t_payload_off and
+// t_payload (whole lines); only the payload reads are scattered, inside one
+// first-pass segment. One workgroup per CU walks the buckets in column order
+// (all CUs on neighbouring buckets, so their payload sources share a segment
+// held in the memory-side cache). A bucket it does not take (more cells than
+// fit, payload sources spanning 2^32 bytes or more, 2^32 payload bytes or
+// more) is marked 0 in bucket_done and left to k_finish, which skips those
+// marked 1. A bucket of 2^7 columns of the large multigraph holds 8,192 cells
+// on average and at most 8,834, under kBkCap.
+constexpr int kBkBlock = 1024;
+constexpr int kBkNW = kBkBlock / kWave;
+constexpr int kBkItems = 9;                     // cells per lane
+constexpr int kBkCap = kBkBlock * kBkItems;     // cells of a bucket held at once
+constexpr int kBkWaveCells = kBkItems * kWave;  // contiguous cells of one wave
+constexpr int kBkPay = 2;                       // cells per lane whose payload is in flight
+
+struct BucketLds {
+  uint32_t row[kBkCap];              // output order: original row id
+  uint32_t src[kBkCap];              // output order: payload offset above the bucket's lowest
+  uint32_t bp[kBkCap + 1];           // output order: size, then its exclusive prefix
+  uint16_t wc[kFinishCols * kBkNW];  // (column, wave) counts, then their column-major scan
+  uint64_t lo[kBkNW], hi[kBkNW], tot[kBkNW];
+  uint32_t red[kBkNW + 1];
+};
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const uint64_t u = __shfl_xor(v, o, kWave);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) {
+    const uint64_t u = __shfl_xor(v, o, kWave);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// A bucket k_finish_bucket can hold (block-uniform).
+__device__ __forceinline__ bool bucket_loadable(const Seg& s) {
+  return s.key_hi > s.key_lo && s.len > 0 && s.len <= (uint32_t)kBkCap;
+}
+
+// The bucket's 16-byte packed records, wave w holding cells
+// [w * kBkWaveCells, (w + 1) * kBkWaveCells) (clamped into the bucket).
+__device__ __forceinline__ void load_bucket(v4u (&r)[kBkItems], const uint32_t* rso, const Seg& s,
+                                            uint32_t tid) {
+  const uint32_t w = tid / kWave, lane = tid % kWave;
+#pragma unroll
+  for (int q = 0; q < kBkItems; ++q) {
+    const uint32_t i = min(w * kBkWaveCells + q * kWave + lane, s.len - 1);
+    r[q] = gm((const v4u*)rso)[s.cell0 + i];
+  }
+}
+
+__device__ __forceinline__ void zero_bucket(v4u (&r)[kBkItems]) {
+#pragma unroll
+  for (int q = 0; q < kBkItems; ++q) r[q] = v4u{0u, 0u, 0u, 0u};
+}
+
+__global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
+  __shared__ BucketLds L;
+  if (aborted(a.abort_flag) || !packed_records(a.pk_on, a.no_pack)) return;
+  const uint32_t nb = a.nbuckets;
+  uint32_t bk = blockIdx.x;
+  if (bk >= nb) return;
+  const int ow = a.offset_width;
+  Seg sg = a.buckets[bk];
+  for (; bk < nb; bk += gridDim.x) {
+    // the thread index, opaque to the compiler inside each iteration: the
+    // per-cell indexes derived from it are recomputed here instead of being
+    // hoisted out of the loop (and spilled)
+    const uint32_t tid = settled((uint32_t)threadIdx.x);
+    const uint32_t w = tid / kWave, lane = tid % kWave;
+    const uint32_t bn = bk + gridDim.x;
+    Seg sn = sg;
+    if (bn < nb) sn = a.buckets[bn];
+    v4u cur[kBkItems];
+    if (bucket_loadable(sg)) load_bucket(cur, a.rso_in, sg, tid);
+    else zero_bucket(cur);
+    const ItemDev* it = &a.items[sg.item];
+    const uint32_t nc = sg.key_hi - sg.key_lo;
+    const uint32_t len = sg.len;
+    const bool take = nc > 0 && len <= (uint32_t)kBkCap;  // block-uniform
+    const uint64_t out_cell0 = sg.cell0 - it->cell_base;
+    const uint64_t out_byte0 = sg.byte0 - it->byte_base;
+    const int pk_shift = it->pk_shift;
+    const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
+    bool fits = false;
+    uint64_t blo = 0;
+    if (take) {
+      // digits, the lowest and highest payload byte and the total
+      uint32_t dg[kBkItems], rank[kBkItems];
+      uint64_t lo = ~0ull, hi = 0, tb = 0;
+#pragma unroll
+      for (int q = 0; q < kBkItems; ++q) {
+        const uint32_t i = w * kBkWaveCells + q * kWave + lane;
+        const uint32_t x = cur[q].x;
+        const uint32_t sz = x >> pk_shift;
+        const uint64_t off = (uint64_t)cur[q].z | ((uint64_t)cur[q].w << 32);
+        uint32_t d = (x & pk_mask) - sg.key_lo;
+        d = d < nc ? d : nc - 1;
+        dg[q] = i < len ? d : 0u;
+        if (i < len) {
+          lo = off < lo ? off : lo;
+          hi = off + sz > hi ? off + sz : hi;
+          tb += sz;
+        }
+      }
+      lo = wave_min_u64(lo);
+      hi = wave_max_u64(hi);
+      tb = wave_sum_u64(tb);
+      if (lane == 0) {
+        L.lo[w] = lo;
+        L.hi[w] = hi;
+        L.tot[w] = tb;
+      }
+      const uint32_t E = nc * kBkNW;
+      for (uint32_t e = tid; e < E; e += kBkBlock) L.wc[e] = 0;
+      __syncthreads();
+      uint64_t bhi = 0, btot = 0;
+      blo = ~0ull;
+#pragma unroll
+      for (int q = 0; q < kBkNW; ++q) {
+        blo = L.lo[q] < blo ? L.lo[q] : blo;
+        bhi = L.hi[q] > bhi ? L.hi[q] : bhi;
+        btot += L.tot[q];
+      }
+      fits = len == 0 || (bhi - blo < (1ull << 32) && btot < (1ull << 32));
+      if (len == 0) blo = 0;
+      if (fits) {
+        // stable ranks: per (column, wave) counters, each wave in cell order
+        const int dbits = ceil_log2(nc);
+#pragma unroll
+        for (int q = 0; q < kBkItems; ++q) {
+          const uint32_t i = w * kBkWaveCells + q * kWave + lane;
+          const bool act = i < len;
+          const uint64_t peers = match_peers(dg[q], act, dbits);
+          rank[q] = 0;
+          if (act) {
+            const uint32_t below = popc_below(peers);
+            const uint32_t old = L.wc[dg[q] * kBkNW + w];
+            if (below == 0) L.wc[dg[q] * kBkNW + w] = (uint16_t)(old + (uint32_t)__popcll(peers));
+            rank[q] = old + below;
+          }
+        }
+        __syncthreads();
+        {  // column-major exclusive scan of the counters: each column's first output cell
+          const uint32_t per = (E + kBkBlock - 1) / kBkBlock;
+          const uint32_t e0 = tid * per;
+          uint32_t sum = 0;
+          for (uint32_t e = e0; e < e0 + per && e < E; ++e) sum += L.wc[e];
+          uint32_t tot;
+          uint32_t ex = block_excl_scan<kBkNW>(sum, L.red, tot);
+          for (uint32_t e = e0; e < e0 + per && e < E; ++e) {
+            const uint32_t v = L.wc[e];
+            L.wc[e] = (uint16_t)ex;
+            ex += v;
+          }
+        }
+        __syncthreads();
+        for (uint32_t c = tid; c < nc; c += kBkBlock)
+          st_off(it->t_row_ptr, (uint64_t)sg.key_lo + c, (int64_t)(out_cell0 + L.wc[c * kBkNW]), ow);
+#pragma unroll
+        for (int q = 0; q < kBkItems; ++q) {
+          const uint32_t i = w * kBkWaveCells + q * kWave + lane;
+          if (i < len) {
+            const uint32_t p = (uint32_t)L.wc[dg[q] * kBkNW + w] + rank[q];
+            const uint64_t off = (uint64_t)cur[q].z | ((uint64_t)cur[q].w << 32);
+            L.row[p] = cur[q].y;
+            L.src[p] = (uint32_t)(off - blo);
+            L.bp[p] = cur[q].x >> pk_shift;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    if (take && fits) {
+      {  // sizes -> exclusive byte prefix in output order (kBkItems positions per lane)
+        uint32_t v[kBkItems];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int q = 0; q < kBkItems; ++q) {
+          const uint32_t p = tid * kBkItems + q;
+          v[q] = p < len ? L.bp[p] : 0u;
+          sum += v[q];
+        }
+        uint32_t tot;
+        uint32_t ex = block_excl_scan<kBkNW>(sum, L.red, tot);
+#pragma unroll
+        for (int q = 0; q < kBkItems; ++q) {
+          const uint32_t p = tid * kBkItems + q;
+          if (p < len) L.bp[p] = ex;
+          ex += v[q];
+        }
+        if (tid == 0) L.bp[len] = tot;
+        __syncthreads();
+      }
+      // outputs in output order, kBkPay cells per lane with their payload
+      // loads in flight before the stores
+      uint8_t* const o_pay = it->t_payload;
+      int32_t* const o_col = it->t_col;
+      void* const o_poff = it->t_poff;
+      const uint8_t* const src_base = a.pay_in + blo;
+#pragma unroll
+      for (int g = 0; g < kBkItems; g += kBkPay) {
+        uint8_t* pd[kBkPay];
+        const uint8_t* ps[kBkPay];
+        uint32_t pz[kBkPay], pr[kBkPay], pb[kBkPay];
+#pragma unroll
+        for (int q = 0; q < kBkPay; ++q) {
+          const uint32_t p = (uint32_t)(g + q) * kBkBlock + tid;
+          pz[q] = 0;
+          pr[q] = 0;
+          pb[q] = 0;
+          pd[q] = o_pay;
+          ps[q] = src_base;
+          if (p < len) {
+            pb[q] = L.bp[p];
+            pz[q] = L.bp[p + 1] - pb[q];
+            pr[q] = L.row[p];
+            pd[q] = o_pay + out_byte0 + pb[q];
+            ps[q] = src_base + L.src[p];
+          }
+        }
+        PayRegsT<kBkPay> P;
+        pay_load(P, pd, ps, pz);
+#pragma unroll
+        for (int q = 0; q < kBkPay; ++q) {
+          const uint32_t p = (uint32_t)(g + q) * kBkBlock + tid;
+          if (p < len) {
+            gm(o_col)[out_cell0 + p] = (int32_t)pr[q];
+            if (o_poff) st_off(o_poff, out_cell0 + p, (int64_t)(out_byte0 + pb[q]), ow);
+          }
+        }
+        pay_store(P, pd, ps, pz);
+      }
+    }
+    if (tid == 0) a.bucket_done[bk] = (take && fits) ? 1 : 0;
+    __syncthreads();  // LDS is reused by the next bucket
+    sg = sn;
+  }
 }
 
 // ----------------------------------------------------------------------------- children
@@ -1801,6 +2067,13 @@ hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s) {
 
 hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
   if (a.nseg) hipLaunchKernelGGL(G::k_children, grid1(a.nseg), dim3(G::kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_bucket(const FinishArgs& a, hipStream_t s) {
+  if (a.nbuckets && a.bucket_done && a.grid)
+    hipLaunchKernelGGL(G::k_finish_bucket, dim3(a.grid < a.nbuckets ? a.grid : a.nbuckets),
+                       dim3(G::kBkBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -184,6 +184,7 @@ struct Layout {
       o_hstart[kMaxLevels];
   uint64_t o_hcnt, o_hbyt, o_ocnt, o_obyt, o_ttot, o_tsrc, o_scan;
   uint64_t o_ks[2], o_rk[2], o_pay[2], o_rso = 0;
+  uint64_t o_bdone = 0;  // two or more passes: per finish bucket, written by k_finish_bucket
   // view operations: partition bounds of the matrix, per-cell keys and values
   uint64_t n_vbounds = 0, o_vbounds = 0, o_vkeys = 0, o_vvals = 0;
   uint64_t o_up_end = 0;  // the uploaded prefix: items, status, bounds, level-0 tables
@@ -304,7 +305,10 @@ Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
     y.o_rk[b] = b < nrk ? take(8ull * y.total_nnz) : y.o_rk[0];
     y.o_pay[b] = b < nrk ? take(y.total_bytes + 16) : y.o_pay[0];
   }
-  if (L >= 2) y.o_rso = take(16ull * y.total_nnz);
+  if (L >= 2) {
+    y.o_rso = take(16ull * y.total_nnz);
+    y.o_bdone = take(y.nseg[L]);
+  }
   if (n_vbounds) {
     y.o_vkeys = take(4ull * y.total_nnz);
     y.o_vvals = take(4ull * y.total_nnz);
@@ -406,6 +410,20 @@ void time_mark(mgt_plan_s* p, hipStream_t s, const char* name) {
   t.names[t.used] = name;
   (void)hipEventRecord(t.ev[t.used], s);
   ++t.used;
+}
+
+// Compute units of the current device (read once per device).
+uint32_t device_cus() {
+  static uint32_t cus[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cus[dev]) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+      n = 256;
+    cus[dev] = (uint32_t)n;
+  }
+  return cus[dev];
 }
 
 #define MGT_HIP(x)                          \
@@ -649,6 +667,13 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
   f.g8 = align_up(y.nseg[L], 8);
   f.pk_on = pk_on;
   f.no_pack = d_no_pack;
+  if (pk_on && f.rso_in) {
+    // packed records: whole buckets first, the rest (and the tails) after
+    f.bucket_done = W + y.o_bdone;
+    f.grid = device_cus();
+    MGT_HIP(launch_finish_bucket(f, s));
+    time_mark(p, s, "finishb");
+  }
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
 

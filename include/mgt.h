@@ -367,6 +367,36 @@ int mgt_batch_graph_create(mgt_plan_t batch_plan, const mgt_item* items, int32_t
 int mgt_graph_launch(mgt_graph_t graph, hipStream_t stream);
 int mgt_graph_destroy(mgt_graph_t graph);
 
+/* ------------------------------------------------------------------ no allocation */
+
+/*
+ * For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation. The same transpose as
+ * mgt_transpose (partitioned == 0) or mgt_transpose_partitioned (partitioned
+ * != 0), with the same arguments, outputs and errors, except that there is no
+ * workspace argument: every call uses the library's own device array of
+ * MGT_NOALLOC_SCRATCH_BYTES bytes on the current device (each GPU the library
+ * runs on holds its own until the process ends). The call allocates nothing
+ * (no device or pinned memory, no events) and hands the plan's descriptor to
+ * the device through kernel arguments.
+ *   - A plan whose transpose needs more workspace than that (the size
+ *     mgt_plan reported for this form) gives MGT_ENOMEM before anything is
+ *     launched; plans with MGT_DEBUG_TIMING give MGT_EINVAL.
+ *   - Every call on one GPU shares that GPU's array, and the array keeps the
+ *     last call's contents (no call relies on it starting at zero). Calls whose
+ *     device work may overlap on one GPU (several streams, several threads)
+ *     race on it: order them on one stream, or use mgt_transpose with a
+ *     workspace of its own.
+ */
+#define MGT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mgt_transpose_noalloc(mgt_plan_t plan, int32_t partitioned, const void* row_ptr,
+                          const int32_t* col, const void* payload_off, const uint8_t* payload,
+                          void* t_row_ptr, int32_t* t_col, void* t_payload_off,
+                          uint8_t* t_payload, uint32_t* perm, int64_t* xfer_cells,
+                          int64_t* xfer_bytes, int64_t* part_cell_off, int64_t* part_byte_off,
+                          int64_t* sdispls, int64_t* rdispls, int32_t* d_status,
+                          hipStream_t stream);
+
 /* ------------------------------------------------------------------ utilities */
 
 /* Per-stage device times of the last call made with MGT_DEBUG_TIMING

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mgt.h"
 #include "mgt_internal.h"
 
 namespace mgt {
@@ -102,6 +103,10 @@ struct FinishArgs {
   uint32_t grid;              // k_finish_bucket: workgroups (one per CU)
 };
 
+// Copies n bytes (a multiple of 4) from host memory to dst through kernel
+// arguments, in chunks of kUploadChunk bytes: no staging buffer, no memcpy.
+constexpr uint32_t kUploadChunk = 3072;
+hipError_t launch_upload(void* dst, const void* src, size_t n, hipStream_t s);
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
                            int32_t* item_status, int32_t* abort_flag, int32_t offset_width,
                            hipStream_t s);
@@ -137,6 +142,13 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 // Whole-bucket finish of a gathering call with packed records (runs before
 // launch_finish, which then skips the buckets it wrote).
 hipError_t launch_finish_bucket(const FinishArgs& a, hipStream_t s);
+// The allocation-free transpose (runtime.cpp), called by mgt_transpose_noalloc.
+int noalloc_call(mgt_plan_t p, int32_t partitioned, const void* row_ptr, const int32_t* col,
+                 const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,
+                 void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xfer_cells,
+                 int64_t* xfer_bytes, int64_t* part_cell_off, int64_t* part_byte_off,
+                 int64_t* sdispls, int64_t* rdispls, void* ws, size_t ws_bytes, int32_t* d_status,
+                 hipStream_t stream);
 // Scratch needed by launch_scan for n_max elements (bytes).
 inline uint64_t scan_scratch_bytes(uint64_t n_max) {
   return 2 * 8 * ((n_max + kScanBlock - 1) / kScanBlock + 1) + 64;

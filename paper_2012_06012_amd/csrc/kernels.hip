@@ -7,6 +7,8 @@
 // counting sort in LDS; see mgt_internal.h for the data flow.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "../../include/mgt.h"
 #include "kernels.h"
 #include "prims.h"
@@ -223,6 +225,20 @@ __device__ __forceinline__ bool packed_records(int32_t pk_on, const int32_t* no_
 
 // (the 512-thread copy of this file needs only the records-only scatter)
 #ifndef MGT_WIDE
+// ----------------------------------------------------------------------------- upload
+
+// Bytes handed over as a kernel argument, copied word by word to dst.
+struct UploadArgs {
+  uint32_t* dst;
+  uint32_t words;
+  uint32_t pad;
+  uint32_t data[kUploadChunk / 4];
+};
+
+__global__ __launch_bounds__(kBlock) void k_upload(UploadArgs a) {
+  for (uint32_t i = threadIdx.x; i < a.words; i += kBlock) gm(a.dst)[i] = a.data[i];
+}
+
 // ----------------------------------------------------------------------------- init / validate
 
 // Device-side data checks (MGT_VALIDATE): offsets start at 0, never decrease
@@ -2007,6 +2023,20 @@ hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 #else
+hipError_t launch_upload(void* dst, const void* src, size_t n, hipStream_t s) {
+  const uint8_t* h = (const uint8_t*)src;
+  for (size_t o = 0; o < n; o += kUploadChunk) {
+    G::UploadArgs a;
+    const size_t c = n - o < kUploadChunk ? n - o : kUploadChunk;
+    a.dst = (uint32_t*)((uint8_t*)dst + o);
+    a.words = (uint32_t)((c + 3) / 4);
+    a.pad = 0;
+    std::memcpy(a.data, h + o, c);
+    hipLaunchKernelGGL(G::k_upload, dim3(1), dim3(G::kBlock), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_validate(const ItemDev* items, uint32_t n_items, uint64_t max_len,
                            int32_t* item_status, int32_t* abort_flag, int32_t ow, hipStream_t s) {
   uint64_t gx = (max_len + 1 + G::kBlock * 16 - 1) / (G::kBlock * 16);

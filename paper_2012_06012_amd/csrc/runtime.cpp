@@ -31,6 +31,10 @@ constexpr uint32_t kMaxPartFanout = 512;  // largest preferred fan-out of the pa
 // of payload over 256 partitions: 512).
 constexpr uint64_t kSegPayloadTarget = 48ull << 20;
 constexpr int kMaxItems = 65535;
+// Host bytes of one single-matrix descriptor upload built on the stack by the
+// allocation-free call (item, status, flags, 1,025 partition bounds and the
+// first-pass tables, each 256-byte aligned, fit with room to spare).
+constexpr size_t kNoAllocUpload = 16384;
 static_assert(kTileCells % kSub == 0, "tile geometry");
 
 int ceil_log2_u64(uint64_t x) {
@@ -170,6 +174,20 @@ struct HostItem {
   ItemDev dev;
 };
 
+// The items of one call, as a view (no ownership): a vector's, or an array on
+// the stack for calls that must not allocate.
+struct Items {
+  HostItem* p = nullptr;
+  size_t n = 0;
+  Items(std::vector<HostItem>& v) : p(v.data()), n(v.size()) {}
+  Items(HostItem* a, size_t k) : p(a), n(k) {}
+  HostItem& operator[](size_t i) const { return p[i]; }
+  size_t size() const { return n; }
+  bool empty() const { return n == 0; }
+  HostItem* begin() const { return p; }
+  HostItem* end() const { return p + n; }
+};
+
 // Workspace layout of one call.
 struct Layout {
   uint32_t n_items = 0;
@@ -206,7 +224,7 @@ uint32_t tile_cells_for(uint64_t nnz) {
 
 // n_vbounds > 0: a view operation on the single item, whose matrix has
 // n_vbounds - 1 partitions.
-Layout make_layout(std::vector<HostItem>& items, uint64_t n_vbounds = 0) {
+Layout make_layout(Items items, uint64_t n_vbounds = 0) {
   Layout y;
   y.n_vbounds = n_vbounds;
   y.n_items = (uint32_t)items.size();
@@ -446,8 +464,13 @@ size_t upload_bytes(const Layout& y) { return y.o_up_end; }
 // graph_staging: the call is being recorded into a graph that owns this
 // pinned upload buffer (its contents are read at every replay); the plan's
 // own staging buffer, completion event and stage timing are left alone.
-int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, int32_t* d_status,
-        hipStream_t s, const ViewCall* vc = nullptr, void* graph_staging = nullptr) {
+// kernel_upload: the descriptor is built in this host buffer (at least
+// upload_bytes(y) bytes, 16-byte aligned) and copied to the workspace by
+// kernels taking it as arguments (launch_upload), so the call neither
+// allocates nor touches the plan's pinned staging buffer.
+int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status,
+        hipStream_t s, const ViewCall* vc = nullptr, void* graph_staging = nullptr,
+        uint8_t* kernel_upload = nullptr) {
   uint8_t* W = (uint8_t*)ws;
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
@@ -461,11 +484,11 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
       pk_on = 0;
   // 1. upload items + bounds through the pinned staging buffer
   const size_t up_bytes = upload_bytes(y);
-  if (!graph_staging) {
+  if (!graph_staging && !kernel_upload) {
     int st = ensure_staging(p, up_bytes);
     if (st != MGT_OK) return st;
   }
-  uint8_t* H = (uint8_t*)(graph_staging ? graph_staging : p->staging);
+  uint8_t* H = kernel_upload ? kernel_upload : (uint8_t*)(graph_staging ? graph_staging : p->staging);
   int64_t* hb = (int64_t*)(H + y.o_bounds);
   uint64_t bo = 0;
   for (uint32_t i = 0; i < n; ++i) {
@@ -531,10 +554,14 @@ int run(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws, 
     h_hstart[n] = h_acc;
   }
   time_mark(p, s, "start");
-  MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
-  if (!graph_staging) {
-    MGT_HIP(hipEventRecord(p->upload_done, s));
-    p->upload_pending = true;
+  if (kernel_upload) {
+    MGT_HIP(launch_upload(W, H, up_bytes, s));
+  } else {
+    MGT_HIP(hipMemcpyAsync(W, H, up_bytes, hipMemcpyHostToDevice, s));
+    if (!graph_staging) {
+      MGT_HIP(hipEventRecord(p->upload_done, s));
+      p->upload_pending = true;
+    }
   }
 
   const ItemDev* d_items = (const ItemDev*)(W + y.o_items);
@@ -713,7 +740,7 @@ int check_io(const mgt_desc& d, uint32_t flags, const void* row_ptr, const int32
 // Records one call into g: the pinned upload buffer and a private stream are
 // made first (nothing is allocated while capturing), then the call is
 // captured on that stream and instantiated.
-int record_graph(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, void* ws,
+int record_graph(mgt_plan_s* p, Items items, const Layout& y, void* ws,
                  int32_t* d_status, mgt_graph_s* g) {
   if (hipHostMalloc(&g->staging, upload_bytes(y), hipHostMallocDefault) != hipSuccess) {
     g->staging = nullptr;
@@ -738,12 +765,17 @@ int record_graph(mgt_plan_s* p, std::vector<HostItem>& items, const Layout& y, v
   return st;
 }
 
+// no_alloc: the call allocates nothing (no pinned staging, no events, no heap):
+// plans with MGT_DEBUG_TIMING are refused and the descriptor goes up through
+// kernel arguments.
 int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int32_t* col,
                 const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,
                 void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xc, int64_t* xb,
                 int64_t* pco, int64_t* pbo, int64_t* sd, int64_t* rd, void* ws, size_t ws_bytes,
-                int32_t* d_status, hipStream_t s, mgt_graph_s* graph = nullptr) {
+                int32_t* d_status, hipStream_t s, mgt_graph_s* graph = nullptr,
+                bool no_alloc = false) {
   if (!p || p->batch || p->view_op >= 0) return MGT_EINVAL;
+  if (no_alloc && (p->flags & MGT_DEBUG_TIMING)) return MGT_EINVAL;
   const mgt_desc& d = p->desc;
   int st = check_io(d, p->flags, row_ptr, col, payload_off, payload, t_row_ptr, t_col, t_payload_off,
                     t_payload, perm);
@@ -753,7 +785,7 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
   // The schedule is read under the plan's lock (mgt_plan_set_schedule may
   // change it from another thread) and the lock is held through the launches.
   std::lock_guard<std::mutex> lock(p->mu);
-  std::vector<HostItem> items(1);
+  HostItem items[1] = {};
   HostItem& it = items[0];
   it.d = d;
   it.bounds = p->bounds.empty() ? nullptr : p->bounds.data();
@@ -772,11 +804,16 @@ int single_call(mgt_plan_s* p, bool partitioned, const void* row_ptr, const int3
     it.dev.rdispls = rd;
   }
   if (!partitioned) it.bounds = nullptr;
-  Layout y = make_layout(items);
+  Layout y = make_layout(Items(items, 1));
   if (ws_bytes < y.bytes) return MGT_ENOMEM;
-  if (graph) return record_graph(p, items, y, ws, d_status, graph);
+  if (graph) return record_graph(p, Items(items, 1), y, ws, d_status, graph);
   p->timing.used = 0;
-  return run(p, items, y, ws, d_status, s);
+  if (no_alloc) {
+    alignas(16) uint8_t up[kNoAllocUpload];
+    if (upload_bytes(y) > sizeof(up)) return MGT_EUNSUPPORTED;
+    return run(p, Items(items, 1), y, ws, d_status, s, nullptr, nullptr, up);
+  }
+  return run(p, Items(items, 1), y, ws, d_status, s);
 }
 
 size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned, const Tune& t) {
@@ -835,6 +872,24 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
 }
 
 }  // namespace
+
+namespace mgt {
+// The allocation-free transpose behind mgt_transpose_noalloc (noalloc.hip),
+// on a workspace the caller guarantees (the library's scratch array).
+int noalloc_call(mgt_plan_s* p, int32_t partitioned, const void* row_ptr, const int32_t* col,
+                 const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,
+                 void* t_payload_off, uint8_t* t_payload, uint32_t* perm, int64_t* xfer_cells,
+                 int64_t* xfer_bytes, int64_t* part_cell_off, int64_t* part_byte_off,
+                 int64_t* sdispls, int64_t* rdispls, void* ws, size_t ws_bytes, int32_t* d_status,
+                 hipStream_t stream) {
+  if (partitioned && p && !p->batch && p->desc.n_parts > 1 && p->desc.n_rows != p->desc.n_cols)
+    return MGT_EINVAL;
+  return single_call(p, partitioned != 0, row_ptr, col, payload_off, payload, t_row_ptr, t_col,
+                     t_payload_off, t_payload, perm, xfer_cells, xfer_bytes, part_cell_off,
+                     part_byte_off, sdispls, rdispls, ws, ws_bytes, d_status, stream, nullptr,
+                     true);
+}
+}  // namespace mgt
 
 extern "C" {
 

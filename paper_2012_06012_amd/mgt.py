@@ -88,13 +88,14 @@ _lib.mgt_plan_schedule.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
 _lib.mgt_coalesce.argtypes = [_i64, _i64, _i32] + [_vp] * 9 + [_sz, _vp]
 _lib.mgt_expand.argtypes = [_i64, _i64, _i64, _i32, _i32] + [_vp] * 7 + [_vp]
 _lib.mgt_counts_to_offsets.argtypes = [_i64, _vp, _i32, _i32, _vp, _vp, _sz, _vp]
+_lib.mgt_transpose_noalloc.argtypes = [_vp, _i32] + [_vp] * 17
 _lib.mgt_version.restype = ctypes.c_char_p
 for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
            "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
            "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce", "mgt_expand",
            "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
-           "mgt_plan_schedule"):
+           "mgt_plan_schedule", "mgt_transpose_noalloc"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
@@ -102,7 +103,8 @@ EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_part
             "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
             "mgt_graph_launch", "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce",
             "mgt_expand", "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
-            "mgt_plan_schedule")
+            "mgt_plan_schedule", "mgt_transpose_noalloc")
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MGT_NOALLOC_SCRATCH_BYTES
 
 
 def version() -> str:
@@ -205,6 +207,17 @@ def mgt_transpose(plan: Plan, row_ptr, col, payload_off, payload, t_row_ptr, t_c
                               _ptr(t_payload), _ptr(perm), _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _ptr(d_status),
                               _stream(stream)), "mgt_transpose")
+
+
+def mgt_transpose_noalloc(plan: Plan, partitioned: bool, row_ptr, col, payload_off, payload,
+                          t_row_ptr, t_col, t_payload_off, t_payload, perm, xfer_cells=None,
+                          xfer_bytes=None, part_cell_off=None, part_byte_off=None, sdispls=None,
+                          rdispls=None, d_status=None, stream=None) -> None:
+    _check(_lib.mgt_transpose_noalloc(
+        plan.handle, 1 if partitioned else 0, _ptr(row_ptr), _ptr(col), _ptr(payload_off),
+        _ptr(payload), _ptr(t_row_ptr), _ptr(t_col), _ptr(t_payload_off), _ptr(t_payload),
+        _ptr(perm), _ptr(xfer_cells), _ptr(xfer_bytes), _ptr(part_cell_off), _ptr(part_byte_off),
+        _ptr(sdispls), _ptr(rdispls), _ptr(d_status), _stream(stream)), "mgt_transpose_noalloc")
 
 
 def mgt_transpose_partitioned(plan: Plan, row_ptr, col, payload_off, payload, t_row_ptr, t_col,

@@ -331,6 +331,49 @@ int mgt_counts_to_offsets(int64_t nnz, const uint32_t* counts, int32_t value_byt
                           int32_t offset_width, void* payload_off, void* workspace,
                           size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------ unordered graphs */
+
+/*
+ * Unordered multigraphs stored as one triangle (Section 2: an unordered edge
+ * {i, j, e} gives M_ij = M_ji = e, so the matrix is symmetric and its lower
+ * triangle -- every cell with col <= row -- or its upper triangle -- col >=
+ * row -- holds the whole graph). The triangle's own transpose (lower storage
+ * to upper storage of the same graph and back) is mgt_transpose.
+ *
+ * mgt_symmetrize builds the full symmetric matrix S of a stored triangle:
+ * every stored off-diagonal cell (i, j, e) appears in S as (i, j, e) and as
+ * (j, i, e) with the same payload bytes; a stored diagonal cell (i, i, e)
+ * appears once. Row i of S is, for MGT_LOWER, the stored cells of row i in
+ * their stored order followed by the mirrored cells (i, r) in the order of
+ * their source cells (source row r ascending, then stored order); for
+ * MGT_UPPER the mirrored cells (sources in rows r < i) come first, then the
+ * stored row. Rows stored in column order give rows of S in column order, and
+ * the two storages of one graph give the same S.
+ *   plan     a single-matrix plan (mgt_plan) of the stored triangle: square,
+ *            without MGT_EMIT_PERM, MGT_FIXED_WIDTH or MGT_DEBUG_TIMING (else
+ *            MGT_EINVAL); with MGT_VALIDATE a cell outside the triangle also
+ *            gives *d_status = MGT_ERANGE.
+ *   inputs   the triangle's row_ptr[n+1], col[nnz], payload_off[nnz+1],
+ *            payload[payload_bytes] (device).
+ *   outputs  s_row_ptr[n+1], s_col[2*nnz], s_payload_off[2*nnz+1],
+ *            s_payload[2*payload_bytes] (device; capacities: S holds
+ *            2*nnz - d cells and 2*payload_bytes - b bytes, d and b being the
+ *            diagonal cells and their bytes; entries past those are left
+ *            alone). d_sizes (device int64[2], may be NULL) receives S's cells
+ *            and payload bytes.
+ *   workspace  at least mgt_symmetrize_workspace bytes, 256-byte aligned.
+ * A row of S must hold fewer than 2^32 payload bytes (else *d_status =
+ * MGT_EUNSUPPORTED); with 4-byte offsets 2*nnz and 2*payload_bytes must stay
+ * below 2^31 (else MGT_EUNSUPPORTED). Errors otherwise as for mgt_transpose.
+ */
+enum { MGT_LOWER = 0, MGT_UPPER = 1 };
+int mgt_symmetrize_workspace(mgt_plan_t plan, size_t* workspace_bytes);
+int mgt_symmetrize(mgt_plan_t plan, int32_t triangle, const void* row_ptr, const int32_t* col,
+                   const void* payload_off, const uint8_t* payload, void* s_row_ptr,
+                   int32_t* s_col, void* s_payload_off, uint8_t* s_payload, int64_t* d_sizes,
+                   void* workspace, size_t workspace_bytes, int32_t* d_status,
+                   hipStream_t stream);
+
 /* ------------------------------------------------------------------ graphs */
 
 /*

@@ -7,7 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmgt.so")
-SOURCES = ["kernels.hip", "kernels_wide.hip", "values.hip", "noalloc.hip", "runtime.cpp"]
+SOURCES = ["kernels.hip", "kernels_wide.hip", "values.hip", "symmetric.hip", "noalloc.hip",
+           "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off for every HIP file of the library.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -142,6 +142,37 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 // Whole-bucket finish of a gathering call with packed records (runs before
 // launch_finish, which then skips the buckets it wrote).
 hipError_t launch_finish_bucket(const FinishArgs& a, hipStream_t s);
+// mgt_symmetrize's stages after the transpose of the stored triangle
+// (symmetric.hip). Every offset array has width ow.
+struct SymArgs {
+  uint64_t n, nnz;             // rows (= columns) and stored cells
+  uint64_t pbytes;             // payload bytes of the triangle (and of its transpose)
+  uint64_t cap_cells;          // capacity of s_col (2 nnz) and of s_payload (2 pbytes)
+  uint64_t cap_bytes;
+  int32_t ow, lower, validate;
+  const void* row_ptr;         // the stored triangle
+  const int32_t* col;
+  const void* poff;
+  const uint8_t* payload;
+  const void* t_row_ptr;       // its transpose
+  const int32_t* t_col;
+  const void* t_poff;
+  const uint8_t* t_payload;
+  void* s_row_ptr;             // the full symmetric matrix
+  int32_t* s_col;
+  void* s_poff;
+  uint8_t* s_payload;
+  int64_t* d_sizes;            // cells and payload bytes of S (may be null)
+  int32_t* d_status;           // the caller's status word (may be null)
+  int32_t* st;                 // the call's status: the transpose's, then these stages'
+  uint32_t* cnt;               // per row of S: cells, payload bytes
+  uint32_t* byt;
+  uint64_t* ocnt;              // their exclusive scans (n + 1 entries)
+  uint64_t* obyt;
+  uint64_t* scan;              // scratch of launch_scan for n entries
+};
+hipError_t launch_symmetrize(const SymArgs& a, hipStream_t s);
+
 // The allocation-free transpose (runtime.cpp), called by mgt_transpose_noalloc.
 int noalloc_call(mgt_plan_t p, int32_t partitioned, const void* row_ptr, const int32_t* col,
                  const void* payload_off, const uint8_t* payload, void* t_row_ptr, int32_t* t_col,

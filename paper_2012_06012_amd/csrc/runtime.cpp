@@ -1183,6 +1183,125 @@ int mgt_plan_schedule(mgt_plan_t plan, int32_t partitioned, int32_t* out) {
   return MGT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of mgt_symmetrize: the transpose's own, then the transposed
+// triangle and the per-row counts of S with their scans.
+struct SymLayout {
+  uint64_t o_t_row_ptr, o_t_col, o_t_poff, o_t_pay, o_cnt, o_byt, o_ocnt, o_obyt, o_scan, o_st;
+  uint64_t bytes;
+};
+
+SymLayout sym_layout(const mgt_plan_s* p) {
+  const mgt_desc& d = p->desc;
+  const uint64_t n = (uint64_t)d.n_rows, nnz = (uint64_t)d.nnz, ow = (uint64_t)d.offset_width;
+  SymLayout y{};
+  uint64_t o = align_up(p->ws_plain, 256);
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  y.o_t_row_ptr = take((n + 1) * ow);
+  y.o_t_col = take(4 * nnz);
+  y.o_t_poff = take((nnz + 1) * ow);
+  y.o_t_pay = take((uint64_t)d.payload_bytes + 16);
+  y.o_cnt = take(4 * n);
+  y.o_byt = take(4 * n);
+  y.o_ocnt = take(8 * (n + 1));
+  y.o_obyt = take(8 * (n + 1));
+  y.o_scan = take(scan_scratch_bytes(n));
+  y.o_st = take(64);
+  y.bytes = o;
+  return y;
+}
+
+// A plan mgt_symmetrize takes: a square single-matrix plan without
+// MGT_EMIT_PERM, MGT_FIXED_WIDTH or MGT_DEBUG_TIMING, whose doubled sizes fit
+// its offsets.
+int sym_check_plan(const mgt_plan_s* p) {
+  if (!p || p->batch || p->view_op >= 0) return MGT_EINVAL;
+  const mgt_desc& d = p->desc;
+  if (d.n_rows != d.n_cols) return MGT_EINVAL;
+  if (p->flags & (MGT_EMIT_PERM | MGT_FIXED_WIDTH | MGT_DEBUG_TIMING)) return MGT_EINVAL;
+  if (2 * d.nnz >= (1ll << 32)) return MGT_EUNSUPPORTED;
+  if (d.offset_width == 4 && (2 * d.nnz >= (1ll << 31) || 2 * d.payload_bytes >= (1ll << 31)))
+    return MGT_EUNSUPPORTED;
+  return MGT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mgt_symmetrize_workspace(mgt_plan_t plan, size_t* workspace_bytes) {
+  if (!workspace_bytes) return MGT_EINVAL;
+  const int st = sym_check_plan(plan);
+  if (st != MGT_OK) return st;
+  std::lock_guard<std::mutex> lock(plan->mu);
+  *workspace_bytes = (size_t)sym_layout(plan).bytes;
+  return MGT_OK;
+}
+
+int mgt_symmetrize(mgt_plan_t plan, int32_t triangle, const void* row_ptr, const int32_t* col,
+                   const void* payload_off, const uint8_t* payload, void* s_row_ptr, int32_t* s_col,
+                   void* s_payload_off, uint8_t* s_payload, int64_t* d_sizes, void* workspace,
+                   size_t workspace_bytes, int32_t* d_status, hipStream_t stream) {
+  int st = sym_check_plan(plan);
+  if (st != MGT_OK) return st;
+  if (triangle != MGT_LOWER && triangle != MGT_UPPER) return MGT_EINVAL;
+  const mgt_desc& d = plan->desc;
+  if (!s_row_ptr || !s_payload_off || (d.nnz > 0 && (!s_col || !col)) ||
+      (d.payload_bytes > 0 && (!s_payload || !payload)) || !row_ptr || !payload_off)
+    return MGT_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & 255u)) return MGT_EINVAL;
+  SymLayout y;
+  {
+    std::lock_guard<std::mutex> lock(plan->mu);
+    y = sym_layout(plan);
+  }
+  if (workspace_bytes < y.bytes) return MGT_ENOMEM;
+  uint8_t* W = (uint8_t*)workspace;
+  SymArgs a{};
+  a.n = (uint64_t)d.n_rows;
+  a.nnz = (uint64_t)d.nnz;
+  a.pbytes = (uint64_t)d.payload_bytes;
+  a.cap_cells = 2 * a.nnz;
+  a.cap_bytes = 2 * a.pbytes;
+  a.ow = d.offset_width;
+  a.lower = triangle == MGT_LOWER ? 1 : 0;
+  a.validate = (plan->flags & MGT_VALIDATE) ? 1 : 0;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.poff = payload_off;
+  a.payload = payload;
+  a.t_row_ptr = W + y.o_t_row_ptr;
+  a.t_col = (const int32_t*)(W + y.o_t_col);
+  a.t_poff = W + y.o_t_poff;
+  a.t_payload = W + y.o_t_pay;
+  a.s_row_ptr = s_row_ptr;
+  a.s_col = s_col;
+  a.s_poff = s_payload_off;
+  a.s_payload = s_payload;
+  a.d_sizes = d_sizes;
+  a.d_status = d_status;
+  a.st = (int32_t*)(W + y.o_st);
+  a.cnt = (uint32_t*)(W + y.o_cnt);
+  a.byt = (uint32_t*)(W + y.o_byt);
+  a.ocnt = (uint64_t*)(W + y.o_ocnt);
+  a.obyt = (uint64_t*)(W + y.o_obyt);
+  a.scan = (uint64_t*)(W + y.o_scan);
+  // the stored triangle's transpose (its status word becomes the call's)
+  st = single_call(plan, false, row_ptr, col, payload_off, payload, (void*)a.t_row_ptr,
+                   (int32_t*)a.t_col, (void*)a.t_poff, (uint8_t*)a.t_payload, nullptr, nullptr,
+                   nullptr, nullptr, nullptr, nullptr, nullptr, workspace, plan->ws_plain, a.st,
+                   stream);
+  if (st != MGT_OK) return st;
+  return launch_symmetrize(a, stream) == hipSuccess ? MGT_OK : MGT_EHIP;
+}
+
 int mgt_plan_stage_times(mgt_plan_t plan, float* ms, const char** names, int32_t capacity,
                          int32_t* count) {
   if (!plan || !count) return MGT_EINVAL;

@@ -89,13 +89,16 @@ _lib.mgt_coalesce.argtypes = [_i64, _i64, _i32] + [_vp] * 9 + [_sz, _vp]
 _lib.mgt_expand.argtypes = [_i64, _i64, _i64, _i32, _i32] + [_vp] * 7 + [_vp]
 _lib.mgt_counts_to_offsets.argtypes = [_i64, _vp, _i32, _i32, _vp, _vp, _sz, _vp]
 _lib.mgt_transpose_noalloc.argtypes = [_vp, _i32] + [_vp] * 17
+_lib.mgt_symmetrize_workspace.argtypes = [_vp, ctypes.POINTER(_sz)]
+_lib.mgt_symmetrize.argtypes = [_vp, _i32] + [_vp] * 10 + [_sz, _vp, _vp]
 _lib.mgt_version.restype = ctypes.c_char_p
 for _f in ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
            "mgt_batch_plan", "mgt_batch_workspace", "mgt_batch_submit", "mgt_plan_stage_times",
            "mgt_view_plan", "mgt_view_transform", "mgt_graph_create", "mgt_graph_launch",
            "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce", "mgt_expand",
            "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
-           "mgt_plan_schedule", "mgt_transpose_noalloc"):
+           "mgt_plan_schedule", "mgt_transpose_noalloc", "mgt_symmetrize_workspace",
+           "mgt_symmetrize"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_partitioned",
@@ -103,7 +106,9 @@ EXPORTED = ("mgt_plan", "mgt_plan_destroy", "mgt_transpose", "mgt_transpose_part
             "mgt_version", "mgt_view_plan", "mgt_view_transform", "mgt_graph_create",
             "mgt_graph_launch", "mgt_graph_destroy", "mgt_value_lists_workspace", "mgt_coalesce",
             "mgt_expand", "mgt_counts_to_offsets", "mgt_batch_graph_create", "mgt_plan_set_schedule",
-            "mgt_plan_schedule", "mgt_transpose_noalloc")
+            "mgt_plan_schedule", "mgt_transpose_noalloc", "mgt_symmetrize_workspace",
+            "mgt_symmetrize")
+LOWER, UPPER = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 << 20  # MGT_NOALLOC_SCRATCH_BYTES
 
 
@@ -207,6 +212,45 @@ def mgt_transpose(plan: Plan, row_ptr, col, payload_off, payload, t_row_ptr, t_c
                               _ptr(t_payload), _ptr(perm), _ptr(workspace),
                               workspace.numel() * workspace.element_size(), _ptr(d_status),
                               _stream(stream)), "mgt_transpose")
+
+
+def mgt_symmetrize_workspace(plan: Plan) -> int:
+    ws = _sz()
+    _check(_lib.mgt_symmetrize_workspace(plan.handle, ctypes.byref(ws)), "mgt_symmetrize_workspace")
+    return ws.value
+
+
+def mgt_symmetrize(plan: Plan, triangle: int, row_ptr, col, payload_off, payload, s_row_ptr, s_col,
+                   s_payload_off, s_payload, d_sizes, workspace, d_status=None,
+                   stream=None) -> None:
+    _check(_lib.mgt_symmetrize(plan.handle, triangle, _ptr(row_ptr), _ptr(col), _ptr(payload_off),
+                               _ptr(payload), _ptr(s_row_ptr), _ptr(s_col), _ptr(s_payload_off),
+                               _ptr(s_payload), _ptr(d_sizes), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _ptr(d_status),
+                               _stream(stream)), "mgt_symmetrize")
+
+
+def symmetrize(a: "DeviceCsr", lower: bool = True, validate: bool = False, stream=None):
+    """Full symmetric matrix of the stored triangle `a` (mgt_symmetrize).
+    Returns (outputs sized to S, status tensor); synchronises to read S's size."""
+    plan = plan_for(a, VALIDATE if validate else 0)
+    dev = a.col.device
+    ws = torch.empty(max(mgt_symmetrize_workspace(plan), 256), dtype=torch.uint8, device=dev)
+    odt = torch.int32 if a.offset_width == 4 else torch.int64
+    out = dict(row_ptr=torch.empty(a.n_rows + 1, dtype=odt, device=dev),
+               col=torch.empty(max(2 * a.nnz, 1), dtype=torch.int32, device=dev),
+               payload_off=torch.empty(2 * a.nnz + 1, dtype=odt, device=dev),
+               payload=torch.empty(max(2 * a.payload_bytes, 1), dtype=torch.uint8, device=dev))
+    sizes = torch.zeros(2, dtype=torch.int64, device=dev)
+    status = torch.empty(1, dtype=torch.int32, device=dev)
+    mgt_symmetrize(plan, LOWER if lower else UPPER, a.row_ptr, a.col, a.payload_off, a.payload,
+                   out["row_ptr"], out["col"], out["payload_off"], out["payload"], sizes, ws,
+                   status, stream)
+    torch.cuda.synchronize()
+    m, b = (int(x) for x in sizes.cpu().tolist())
+    out["col"], out["payload_off"], out["payload"] = (out["col"][:m], out["payload_off"][:m + 1],
+                                                      out["payload"][:b])
+    return out, status
 
 
 def mgt_transpose_noalloc(plan: Plan, partitioned: bool, row_ptr, col, payload_off, payload,

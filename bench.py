@@ -241,8 +241,11 @@ def bench_batch(args):
     if cur:
         waves.append(cur)
     log(f"[batch] {n_items} matrices in {len(waves)} waves (budget {args.batch_budget:.3g} B)")
+    from paper_2012_06012_amd import autotune
     tot_cells, ms_b_tot, ms_g_tot, ms_p_tot, same_all = 0, 0.0, 0.0, 0.0, True
+    ms_d_tot = 0.0
     oracle_all = True
+    tuned, tune_report = None, None
     tot_bytes = 0  # algorithmic bytes of every matrix (inputs read once, outputs written once)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     for wi, idx in enumerate(waves):
@@ -257,13 +260,37 @@ def bench_batch(args):
         log(f"[batch] wave {wi}: {len(mats)} matrices, {cells} cells, ready in {time.time() - t0:.1f}s")
         outs, status, plan, ws = mgt.batch_transpose(mats)  # warm-up, allocations
         torch.cuda.synchronize()
+        if tuned is None:
+            # the autotuner on the first wave (the sample batch): digit widths
+            # 4/6/8 and tile sizes, every candidate bit-identical to the rule;
+            # its setting then runs every wave
+            _, tr = autotune.autotune_batch(mats, reps=2, use_cache=False)
+            tuned = (tr.best["pass_bits"], tr.best["tile_cells"])
+            tune_report = {"setting": {"pass_bits": tuned[0], "tile_cells": tuned[1]},
+                           "default_ms_wave0": tr.default_ms, "best_ms_wave0": tr.best["ms"],
+                           "candidates": [{k: t[k] for k in ("pass_bits", "tile_cells", "ms",
+                                                             "bit_exact")} for t in tr.trials]}
+            log(f"[batch] tuned on wave 0: {tune_report}")
         ev0.record()
         for _ in range(args.steps):
             mgt.batch_transpose(mats, plan=plan, workspace=ws, outs=outs)
         ev1.record()
         torch.cuda.synchronize()
-        ms_b = ev0.elapsed_time(ev1) / args.steps
+        ms_d = ev0.elapsed_time(ev1) / args.steps
         ok_status = bool((status.cpu().numpy() == 0).all())
+        # the tuned setting on the same matrices and outputs
+        plan_t = mgt.batch_plan_for(mats)
+        plan_t.set_schedule(tuned[0], -1, tuned[1])
+        _, st_t, _, ws = mgt.batch_transpose(mats, plan=plan_t, workspace=ws, outs=outs)
+        torch.cuda.synchronize()
+        ok_status = ok_status and bool((st_t.cpu().numpy() == 0).all())
+        ev0.record()
+        for _ in range(args.steps):
+            mgt.batch_transpose(mats, plan=plan_t, workspace=ws, outs=outs)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_b = ev0.elapsed_time(ev1) / args.steps
+        plan = plan_t
         # the same submit recorded once as a graph and replayed (same outputs)
         g, _, gst, _, _ = mgt.batch_graph(mats, plan=plan, workspace=ws, outs=outs)
         g.launch()
@@ -315,18 +342,21 @@ def bench_batch(args):
         ok_oracle = _oracle_check(
             [(lambda i=i: gen.batch_item(args.seed, i, 1e3, args.batch_n_hi)) for i in idx], outs)
         oracle_all = oracle_all and ok_oracle
-        log(f"[batch] wave {wi}: batched {ms_b:.1f} ms (graph replay {ms_g:.1f} ms), one by one "
-            f"{ms_p:.1f} ms, batched = one by one {same}, batched = oracle {ok_oracle}")
+        log(f"[batch] wave {wi}: batched {ms_b:.1f} ms tuned ({ms_d:.1f} ms by the rule; graph "
+            f"replay {ms_g:.1f} ms), one by one {ms_p:.1f} ms, batched = one by one {same}, "
+            f"batched = oracle {ok_oracle}")
         tot_cells += cells
         ms_b_tot += ms_b
+        ms_d_tot += ms_d
         ms_g_tot += ms_g
         ms_p_tot += ms_p
         same_all = same_all and same
-        del mats, outs, status, plan, ws, plans, ws1, flat, views, g, gst
+        del mats, outs, status, plan, plan_t, st_t, ws, plans, ws1, flat, views, g, gst
         torch.cuda.empty_cache()
     res = {"metric": "cells/s, batched vs per-matrix plain launches", "mode": "batch",
            "matrices": n_items, "waves": len(waves), "cells": tot_cells,
-           "ms_batched": ms_b_tot, "ms_batched_graph": ms_g_tot, "ms_per_matrix_plain": ms_p_tot,
+           "ms_batched": ms_b_tot, "ms_batched_rule": ms_d_tot, "tuning": tune_report,
+           "ms_batched_graph": ms_g_tot, "ms_per_matrix_plain": ms_p_tot,
            "cells_per_s_batched": tot_cells / (ms_b_tot * 1e-3),
            "cells_per_s_plain": tot_cells / (ms_p_tot * 1e-3), "speedup": ms_p_tot / ms_b_tot,
            "algorithmic_bytes": tot_bytes,

@@ -163,12 +163,17 @@ int mgt_transpose_partitioned(mgt_plan_t plan, const void* row_ptr, const int32_
  * setting that would need more than four passes gives MGT_EUNSUPPORTED.
  * *workspace_bytes (may be NULL) receives the workspace the plan now needs:
  * later calls check against it. Results are the same for every schedule;
- * only the time differs. Batch and view plans give MGT_EINVAL.
+ * only the time differs. On a batch plan the setting applies to every item of
+ * later submits (finish_bits capped by each item's column bits; an item whose
+ * schedule would need more than four passes keeps the rule's), the tile size
+ * to the whole batch, *workspace_bytes receives the plan's estimate again,
+ * and mgt_batch_workspace gives a batch's exact need. View plans give
+ * MGT_EINVAL.
  */
 int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bits,
                           int32_t tile_cells, size_t* workspace_bytes);
 
-/* The schedule a call on this plan uses (host only): out[0] passes,
+/* The schedule a call on this single-matrix plan uses (host only): out[0] passes,
  * out[1..4] bits of each pass (partition passes: sub-bits below the
  * partition), out[5] finish bits, out[6] tile cells, out[7] 1 for a
  * partition-mode first pass. partitioned selects mgt_transpose_partitioned. */

@@ -230,6 +230,8 @@ Layout make_layout(Items items, uint64_t n_vbounds = 0) {
   y.n_items = (uint32_t)items.size();
   if (items.size() == 1)
     y.tile_cells = items[0].tile ? items[0].tile : tile_cells_for((uint64_t)items[0].d.nnz);
+  else if (!items.empty() && items[0].tile)
+    y.tile_cells = items[0].tile;  // a batch plan's tile setting (the same for every item)
   const uint64_t tc = y.tile_cells;
   int L = 1;
   for (auto& it : items) L = std::max(L, it.s.n_levels);
@@ -828,9 +830,23 @@ size_t single_ws(const mgt_desc& d, const int64_t* bounds, bool partitioned, con
   return make_layout(items).bytes;
 }
 
+// Workspace estimate for a batch at the limits; mgt_batch_workspace gives the
+// exact size of a given batch. Level buffers dominate: 2 x (16 B per cell +
+// payload); payload is bounded by the caller, so it is not included here.
+size_t batch_estimate(const mgt_batch_limits& lim) {
+  const uint64_t cells = (uint64_t)lim.max_total_nnz;
+  const uint64_t segs = 2ull * (uint64_t)lim.max_total_cols + cells / 512 + (uint64_t)lim.max_items;
+  return (size_t)(2 * 16 * cells + 4 * segs * (sizeof(Seg) + 24) + 64ull * (cells / 16) + (1u << 20));
+}
+
 int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostItem>& items) {
   if (!p || !p->batch || n < 0 || (n > 0 && !in)) return MGT_EINVAL;
   if (n > p->lim.max_items || n > kMaxItems) return MGT_EUNSUPPORTED;
+  Tune tune;  // the plan's schedule setting, read under its lock
+  {
+    std::lock_guard<std::mutex> lock(p->mu);
+    tune = p->tune;
+  }
   items.resize((size_t)n);
   int64_t tn = 0, tc = 0, tr = 0, tp = 0;
   for (int32_t i = 0; i < n; ++i) {
@@ -853,7 +869,8 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
     it.d = m.desc;
     it.bounds = m.desc.part_bounds;
     it.s = make_sched(m.desc.n_cols, m.desc.nnz, m.desc.payload_bytes, m.desc.n_parts,
-                      m.desc.part_bounds, part, false);
+                      m.desc.part_bounds, part, false, &tune);
+    it.tile = tune.tile;
     fill_outputs(it.dev, m.row_ptr, m.col, m.payload_off, m.payload, m.t_row_ptr, m.t_col,
                  m.t_payload_off, m.t_payload, m.perm);
     if (part) {
@@ -1073,15 +1090,7 @@ int mgt_batch_plan(const mgt_batch_limits* lim, mgt_plan_t* out, size_t* workspa
   p->lim = *lim;
   p->flags = lim->flags;
   *out = p;
-  if (workspace_bytes) {
-    // Estimate for a batch at the limits; mgt_batch_workspace gives the exact
-    // size of a given batch. Level buffers dominate: 2 x (16 B per cell +
-    // payload); payload is bounded by the caller, so it is not included here.
-    const uint64_t cells = (uint64_t)lim->max_total_nnz;
-    const uint64_t segs = 2ull * (uint64_t)lim->max_total_cols + cells / 512 + (uint64_t)lim->max_items;
-    *workspace_bytes = (size_t)(2 * 16 * cells + 4 * segs * (sizeof(Seg) + 24) + 64ull * (cells / 16) +
-                                (1u << 20));
-  }
+  if (workspace_bytes) *workspace_bytes = batch_estimate(*lim);
   return MGT_OK;
 }
 
@@ -1143,7 +1152,7 @@ int mgt_batch_graph_create(mgt_plan_t plan, const mgt_item* items, int32_t n_ite
 
 int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bits,
                           int32_t tile_cells, size_t* workspace_bytes) {
-  if (!plan || plan->batch || plan->view_op >= 0) return MGT_EINVAL;
+  if (!plan || plan->view_op >= 0) return MGT_EINVAL;
   if (pass_bits < 0 || pass_bits > kMaxBitsPerPass) return MGT_EINVAL;
   if (finish_bits < -1 || finish_bits > kMaxFinishBits) return MGT_EINVAL;
   if (tile_cells != 0 && tile_cells != 2048 && tile_cells != 4096 && tile_cells != 8192 &&
@@ -1154,6 +1163,14 @@ int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bit
   t.pass_bits = pass_bits;
   t.finish_bits = finish_bits;
   t.tile = (uint32_t)tile_cells;
+  if (plan->batch) {
+    // applied to every item of later submits (an item whose schedule would
+    // need more than kMaxLevels passes keeps the rule's); the exact
+    // workspace of a batch is mgt_batch_workspace's
+    plan->tune = t;
+    if (workspace_bytes) *workspace_bytes = batch_estimate(plan->lim);
+    return MGT_OK;
+  }
   const mgt_desc& d = plan->desc;
   for (int part = 0; part < 2; ++part) {  // a setting that needs over kMaxLevels passes is refused
     const Sched s = make_sched_mb(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, plan->bounds.data(),

@@ -584,6 +584,15 @@ def batch_entries(mats: Sequence[DeviceCsr], outs: Sequence[dict], perm: bool = 
     return entries, keep
 
 
+def batch_plan_for(mats: Sequence[DeviceCsr], perm: bool = False, validate: bool = False) -> Plan:
+    """A batch plan whose limits are these matrices' totals."""
+    flags = (EMIT_PERM if perm else 0) | (VALIDATE if validate else 0)
+    return mgt_batch_plan(len(mats), sum(a.nnz for a in mats), sum(a.n_cols for a in mats),
+                          sum(a.n_rows for a in mats), sum(a.n_parts for a in mats),
+                          max(a.nnz for a in mats), max(a.n_cols for a in mats),
+                          mats[0].offset_width, flags)
+
+
 def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm: bool = False,
                     validate: bool = False, stream=None, outs=None, workspace=None,
                     done_event=None):
@@ -595,16 +604,13 @@ def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm
     if outs is None:
         outs = [alloc_outputs(a, perm, a.n_parts > 1, dev) for a in mats]
     if plan is None:
-        plan = mgt_batch_plan(len(mats), sum(a.nnz for a in mats), sum(a.n_cols for a in mats),
-                              sum(a.n_rows for a in mats), sum(a.n_parts for a in mats),
-                              max(a.nnz for a in mats), max(a.n_cols for a in mats),
-                              mats[0].offset_width, flags)
+        plan = batch_plan_for(mats, perm, validate)
     entries, keep = batch_entries(mats, outs, perm, flags)
     items = make_items(entries)
     need = mgt_batch_workspace(plan, items)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
-    status = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+    status = torch.empty(len(mats), dtype=torch.int32, device=dev)  # written by the call
     mgt_batch_submit(plan, items, workspace, status, stream, done_event)
     del keep
     return outs, status, plan, workspace
@@ -621,10 +627,7 @@ def batch_graph(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm: bo
     if outs is None:
         outs = [alloc_outputs(a, perm, a.n_parts > 1, dev) for a in mats]
     if plan is None:
-        plan = mgt_batch_plan(len(mats), sum(a.nnz for a in mats), sum(a.n_cols for a in mats),
-                              sum(a.n_rows for a in mats), sum(a.n_parts for a in mats),
-                              max(a.nnz for a in mats), max(a.n_cols for a in mats),
-                              mats[0].offset_width, flags)
+        plan = batch_plan_for(mats, perm, validate)
     entries, keep = batch_entries(mats, outs, perm, flags)
     items = make_items(entries)
     need = mgt_batch_workspace(plan, items)

@@ -298,3 +298,36 @@ def test_plan_schedule_settings():
     v = mgt.mgt_view_plan(10, 10, 5, 0, 8, None, mgt.VIEW_SWAP, mgt.ROW_VIEW)
     with pytest.raises(mgt.MgtError):
         v.set_schedule(8, -1, 0)
+
+
+def test_batch_plan_takes_a_schedule():
+    mgt = _lib()
+    bp = mgt.mgt_batch_plan(8, 1 << 20, 1 << 20, 1 << 20, 8, 1 << 20, 1 << 20, 8)
+    est = bp.workspace_bytes
+    for setting in ((4, -1, 8192), (6, -1, 16384), (8, -1, 0), (0, -1, 0)):
+        assert bp.set_schedule(*setting) == est      # the plan's estimate, unchanged
+    for bad in ((9, -1, 0), (-1, -1, 0), (0, 11, 0), (0, -1, 1000)):
+        with pytest.raises(mgt.MgtError):
+            bp.set_schedule(*bad)
+    with pytest.raises(mgt.MgtError):                 # schedules are read on single-matrix plans
+        bp.schedule()
+
+
+def test_autotune_shape_classes():
+    import numpy as np
+    from paper_2012_06012_amd import autotune
+    mgt = _lib()
+
+    class Fake:  # the fields shape_key reads (no device needed)
+        def __init__(self, nnz, n_cols, pbytes):
+            self.nnz, self.n_cols, self.n_rows, self.payload_bytes = nnz, n_cols, n_cols, pbytes
+            self.offset_width, self.bounds, self.fixed_width = 8, np.array([0, n_cols]), False
+            self.n_parts = 1
+            self.col = type("C", (), {"device": "cpu"})()
+    k1 = autotune.shape_key(Fake(1 << 29, 1 << 23, 9 << 30), False, False)
+    k2 = autotune.shape_key(Fake((1 << 29) + 12345, (1 << 23) - 7, (9 << 30) + 99), False, False)
+    k3 = autotune.shape_key(Fake(1 << 27, 1 << 23, 9 << 28), False, False)
+    assert k1 == k2 and k1 != k3   # one class for nearby shapes, another for 4x fewer cells
+    b1 = autotune.batch_shape_key([Fake(1000, 100, 8000), Fake(3000, 300, 24000)], False)
+    b2 = autotune.batch_shape_key([Fake(1100, 110, 8800), Fake(2900, 290, 23000)], False)
+    assert b1 == b2

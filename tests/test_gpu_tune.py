@@ -47,3 +47,51 @@ def test_autotune_keeps_the_result_and_sets_the_fastest():
     # a second call for the same shape comes from the cache
     plan2, r2 = autotune.autotune(d)
     assert plan2.schedule() == plan.schedule()
+
+
+def _batch_items(seed, n_items):
+    items = []
+    for i in range(n_items):
+        n, deg, width = gen.batch_item_params(seed, i, 100, 30000)
+        a = gen.generate(n, n, seed=(seed << 20) + i, deg_law=gen.DEG_POISSON,
+                         deg_mean=float(min(deg, 24)), pay_law=gen.PAY_BYTES, w_lo=width,
+                         w_hi=width, offset_width=8, name=f"item{i}")
+        if i % 4 == 1:
+            a.bounds = gen.equal_bounds(n, min(n, 3 + i % 5))
+        items.append(a)
+    return items
+
+
+@pytest.mark.parametrize("setting", [(4, -1, 0), (6, -1, 8192), (8, -1, 16384), (4, -1, 2048),
+                                     (5, 3, 4096)])
+@pytest.mark.parametrize("perm", [False, True])
+def test_batch_schedules_match_oracle(setting, perm):
+    """A batch plan's schedule setting (digit widths 4/6/8, tile sizes, an exact
+    finish width) applies to every item; each item still equals the oracle."""
+    from paper_2012_06012_amd import mgt
+    items = _batch_items(11, 14)
+    mats = [to_device(a) for a in items]
+    plan = mgt.batch_plan_for(mats, perm)
+    plan.set_schedule(*setting)
+    outs, st, _, _ = mgt.batch_transpose(mats, plan=plan, perm=perm)
+    assert (st.cpu().numpy() == 0).all()
+    for a, o in zip(items, outs):
+        assert_matches_oracle(a, host(o), check_perm=perm, partitioned=a.n_parts > 1)
+
+
+def test_autotune_batch_keeps_the_result():
+    from paper_2012_06012_amd import autotune, mgt
+    items = _batch_items(12, 10)
+    mats = [to_device(a) for a in items]
+    plan, r = autotune.autotune_batch(mats, reps=2, pass_bits=(4, 8), tiles=(8192, 16384),
+                                      use_cache=False)
+    assert len(r.trials) == 4 and all(t["bit_exact"] for t in r.trials)
+    assert r.best["ms"] <= r.default_ms
+    outs, st, _, _ = mgt.batch_transpose(mats, plan=plan)
+    assert (st.cpu().numpy() == 0).all()
+    for a, o in zip(items, outs):
+        assert_matches_oracle(a, host(o), check_perm=False, partitioned=a.n_parts > 1)
+    # the same batch shape class comes from the cache
+    plan2, r2 = autotune.autotune_batch(mats)
+    assert r2.best["pass_bits"] == r.best["pass_bits"]
+    assert r2.best["tile_cells"] == r.best["tile_cells"]

@@ -29,18 +29,30 @@ _MT_LIB = os.path.join(_HERE, "libscantrans.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EUNSUPPORTED = 0, -1, -2, -3, -5
 
+# MGT_HOST_SANITIZE=1 builds and loads copies instrumented with the address
+# and undefined-behaviour sanitizers instead (the process must then preload
+# the address sanitizer's runtime; tests/test_sanitizers.py does).
+SANITIZE = os.environ.get("MGT_HOST_SANITIZE", "") == "1"
+SANITIZE_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+if SANITIZE:
+    _LIB = _LIB.replace(".so", "_san.so")
+    _MT_LIB = _MT_LIB.replace(".so", "_san.so")
+
 
 def build(force: bool = True) -> str:
     """Compile the oracle (plain C, gcc) in place."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", _SRC,
+        opt = SANITIZE_FLAGS if SANITIZE else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c99", "-Wall", "-fPIC", "-shared", _SRC,
                                "-o", tmp])
         os.replace(tmp, _LIB)
     if force or not os.path.exists(_MT_LIB) or \
             os.path.getmtime(_MT_LIB) < os.path.getmtime(_MT_SRC):
         tmp = _MT_LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O3", "-std=gnu99", "-Wall", "-fPIC", "-shared", "-pthread",
+        opt = SANITIZE_FLAGS if SANITIZE else ["-O3"]
+        subprocess.check_call(["gcc", *opt, "-std=gnu99", "-Wall", "-fPIC", "-shared", "-pthread",
                                _MT_SRC, "-o", tmp])
         os.replace(tmp, _MT_LIB)
     return _LIB

@@ -235,18 +235,20 @@ def symmetrize(a: "DeviceCsr", lower: bool = True, validate: bool = False, strea
     Returns (outputs sized to S, status tensor); synchronises to read S's size."""
     plan = plan_for(a, VALIDATE if validate else 0)
     dev = a.col.device
-    ws = torch.empty(max(mgt_symmetrize_workspace(plan), 256), dtype=torch.uint8, device=dev)
+    ws = _empty(max(mgt_symmetrize_workspace(plan), 256), torch.uint8, dev)
     odt = torch.int32 if a.offset_width == 4 else torch.int64
-    out = dict(row_ptr=torch.empty(a.n_rows + 1, dtype=odt, device=dev),
-               col=torch.empty(max(2 * a.nnz, 1), dtype=torch.int32, device=dev),
-               payload_off=torch.empty(2 * a.nnz + 1, dtype=odt, device=dev),
-               payload=torch.empty(max(2 * a.payload_bytes, 1), dtype=torch.uint8, device=dev))
+    out = dict(row_ptr=_empty(a.n_rows + 1, odt, dev),
+               col=_empty(2 * a.nnz, torch.int32, dev),
+               payload_off=_empty(2 * a.nnz + 1, odt, dev),
+               payload=_empty(2 * a.payload_bytes, torch.uint8, dev))
     sizes = torch.zeros(2, dtype=torch.int64, device=dev)
     status = torch.empty(1, dtype=torch.int32, device=dev)
     mgt_symmetrize(plan, LOWER if lower else UPPER, a.row_ptr, a.col, a.payload_off, a.payload,
                    out["row_ptr"], out["col"], out["payload_off"], out["payload"], sizes, ws,
                    status, stream)
     torch.cuda.synchronize()
+    if _debug():
+        check_guards(list(out.values()) + [ws], "symmetrize")
     m, b = (int(x) for x in sizes.cpu().tolist())
     out["col"], out["payload_off"], out["payload"] = (out["col"][:m], out["payload_off"][:m + 1],
                                                       out["payload"][:b])
@@ -436,6 +438,51 @@ class DeviceCsr:
         return int(len(self.bounds)) - 1
 
 
+# Debug guard words (MGT_DEBUG=1 in the environment): every output and
+# workspace buffer the helpers below allocate is followed by GUARD_BYTES of a
+# fixed pattern, and the call helpers check, after each call, that no byte of
+# those zones changed (a write past the end of an array). Off by default.
+GUARD_BYTES = 4096
+GUARD_PATTERN = 0xA5
+
+
+def _debug() -> bool:
+    return os.environ.get("MGT_DEBUG", "") == "1"
+
+
+def _empty(shape, dtype, device) -> torch.Tensor:
+    """torch.empty, with a guard zone after the tensor's bytes under MGT_DEBUG."""
+    if not _debug():
+        return torch.empty(shape, dtype=dtype, device=device)
+    n = 1
+    for x in (shape if isinstance(shape, tuple) else (shape,)):
+        n *= int(x)
+    item = torch.empty(0, dtype=dtype).element_size()
+    base = torch.empty(n * item + GUARD_BYTES, dtype=torch.uint8, device=device)
+    base[n * item:].fill_(GUARD_PATTERN)
+    t = base[:n * item].view(dtype).view(shape)
+    t._mgt_guard = (base, n * item)
+    return t
+
+
+class GuardError(RuntimeError):
+    pass
+
+
+def check_guards(tensors, what: str = "") -> None:
+    """Raises GuardError if a guard zone after any of `tensors` changed
+    (tensors without one are skipped). Synchronises the device."""
+    gs = [t._mgt_guard for t in tensors if t is not None and hasattr(t, "_mgt_guard")]
+    if not gs:
+        return
+    torch.cuda.synchronize()
+    for base, off in gs:
+        z = base[off:]
+        if not bool((z == GUARD_PATTERN).all()):
+            bad = int(torch.nonzero(z != GUARD_PATTERN)[0])
+            raise GuardError(f"{what}: byte {bad} past the end of a {off}-byte buffer was written")
+
+
 def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, device=None,
                   payload_off: bool = True):
     """Output tensors for `a`. payload_off=False leaves out t_payload_off (only
@@ -443,21 +490,20 @@ def alloc_outputs(a: DeviceCsr, perm: bool = False, partitioned: bool = False, d
     dev = device or a.col.device
     odt = torch.int32 if a.offset_width == 4 else torch.int64
     out = dict(
-        t_row_ptr=torch.empty(a.n_cols + 1, dtype=odt, device=dev),
-        t_col=torch.empty(a.nnz, dtype=torch.int32, device=dev),
-        t_payload_off=(torch.empty(a.nnz + 1, dtype=odt, device=dev)
-                       if payload_off or not a.fixed_width else None),
-        t_payload=torch.empty(a.payload_bytes, dtype=torch.uint8, device=dev),
-        perm=torch.empty(a.nnz, dtype=torch.int32, device=dev) if perm else None,
+        t_row_ptr=_empty(a.n_cols + 1, odt, dev),
+        t_col=_empty(a.nnz, torch.int32, dev),
+        t_payload_off=(_empty(a.nnz + 1, odt, dev) if payload_off or not a.fixed_width else None),
+        t_payload=_empty(a.payload_bytes, torch.uint8, dev),
+        perm=_empty(a.nnz, torch.int32, dev) if perm else None,
     )
     if partitioned:
         R = a.n_parts
-        out.update(xfer_cells=torch.empty((R, R), dtype=torch.int64, device=dev),
-                   xfer_bytes=torch.empty((R, R), dtype=torch.int64, device=dev),
-                   part_cell_off=torch.empty(R + 1, dtype=torch.int64, device=dev),
-                   part_byte_off=torch.empty(R + 1, dtype=torch.int64, device=dev),
-                   sdispls=torch.empty((R, R), dtype=torch.int64, device=dev),
-                   rdispls=torch.empty((R, R), dtype=torch.int64, device=dev))
+        out.update(xfer_cells=_empty((R, R), torch.int64, dev),
+                   xfer_bytes=_empty((R, R), torch.int64, dev),
+                   part_cell_off=_empty(R + 1, torch.int64, dev),
+                   part_byte_off=_empty(R + 1, torch.int64, dev),
+                   sdispls=_empty((R, R), torch.int64, dev),
+                   rdispls=_empty((R, R), torch.int64, dev))
     return out
 
 
@@ -469,7 +515,7 @@ def plan_for(a: DeviceCsr, flags: int = 0) -> Plan:
 
 def workspace_for(plan: Plan, device) -> torch.Tensor:
     # torch's caching allocator returns 256-byte aligned blocks
-    return torch.empty(max(plan.workspace_bytes, 256), dtype=torch.uint8, device=device)
+    return _empty(max(plan.workspace_bytes, 256), torch.uint8, device)
 
 
 def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: bool = False,
@@ -502,6 +548,8 @@ def transpose(a: DeviceCsr, plan: Optional[Plan] = None, workspace=None, perm: b
         mgt_transpose(plan, a.row_ptr, a.col, a.payload_off, a.payload, out["t_row_ptr"],
                       out["t_col"], out["t_payload_off"], out["t_payload"], out["perm"],
                       workspace, status, stream)
+    if _debug():
+        check_guards(list(out.values()) + [workspace], "transpose")
     return out, status
 
 
@@ -609,10 +657,12 @@ def batch_transpose(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm
     items = make_items(entries)
     need = mgt_batch_workspace(plan, items)
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        workspace = _empty(max(need, 256), torch.uint8, dev)
     status = torch.empty(len(mats), dtype=torch.int32, device=dev)  # written by the call
     mgt_batch_submit(plan, items, workspace, status, stream, done_event)
     del keep
+    if _debug():
+        check_guards([t for o in outs for t in o.values()] + [workspace], "batch_transpose")
     return outs, status, plan, workspace
 
 
@@ -632,7 +682,7 @@ def batch_graph(mats: Sequence[DeviceCsr], plan: Optional[Plan] = None, perm: bo
     items = make_items(entries)
     need = mgt_batch_workspace(plan, items)
     if workspace is None or workspace.numel() < need:
-        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        workspace = _empty(max(need, 256), torch.uint8, dev)
     status = torch.zeros(len(mats), dtype=torch.int32, device=dev)
     g = mgt_batch_graph_create(plan, items, workspace, status, keep=(keep, outs, tuple(mats)))
     return g, outs, status, plan, workspace

@@ -3,6 +3,10 @@ import sys
 
 import pytest
 
+# Debug guard words for every GPU test: outputs and workspaces allocated by the
+# binding's helpers carry a guard zone that is checked after each call.
+os.environ.setdefault("MGT_DEBUG", "1")
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -66,11 +66,22 @@ class _Spec(ctypes.Structure):
     ]
 
 
+# MGT_HOST_SANITIZE=1 builds and loads a copy instrumented with the address
+# and undefined-behaviour sanitizers instead (the process must then preload
+# the address sanitizer's runtime; tests/test_sanitizers.py does).
+SANITIZE = os.environ.get("MGT_HOST_SANITIZE", "") == "1"
+SANITIZE_FLAGS = ["-g", "-O1", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+if SANITIZE:
+    _LIB = _LIB.replace(".so", "_san.so")
+
+
 def build(force: bool = True) -> str:
     """Compile the generator library in place (g++, host code only)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread",
+        opt = SANITIZE_FLAGS if SANITIZE else ["-O2"]
+        subprocess.check_call(["g++", *opt, "-std=c++17", "-fPIC", "-shared", "-pthread",
                                _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB

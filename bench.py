@@ -89,7 +89,10 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
 # scaled by what the same counter reads for a plain device copy of known size.
 # A reading holds only for the kernel sources it was taken on; after any change
 # to them the traffic figure is reported as null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "step": {"sources_sha256": "a456f8d6f9eceddc890a10314e0481f294bbb842384ee36922348f1530dcb8a9",
+             "fetch_kib": 38016774.5, "write_kib": 45925645.4},
+}
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
 

@@ -1924,8 +1924,30 @@ __global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
             ps[q] = src_base + L.src[p];
           }
         }
+        // Payloads of dword sizes up to 32 bytes at dword addresses (every cell
+        // of the large workloads) take the staged path: each lane loads its
+        // cell in whole 16-byte pieces (reading up to 12 bytes past it, inside
+        // the level buffer's padding), the wave packs its 64 cells' bytes in
+        // LDS in output order, and writes them back as 16 contiguous bytes
+        // per lane. Other payloads are copied lane by lane.
         PayRegsT<kBkPay> P;
-        pay_load(P, pd, ps, pz);
+        bool staged = true;
+#pragma unroll
+        for (int q = 0; q < kBkPay; ++q)
+          staged &= pz[q] == 0u ||
+                    (pz[q] <= 32u &&
+                     ((pz[q] | (uint32_t)(uintptr_t)ps[q] | (uint32_t)(uintptr_t)pd[q]) & 3u) == 0);
+        staged = __all(staged);
+        if (staged) {
+#pragma unroll
+          for (int q = 0; q < kBkPay; ++q) {
+            const GMEM uint8_t* sp = gm(ps[q]);
+            if (pz[q]) P.v[q][0] = *(const GMEM u32x4a*)sp;
+            if (pz[q] > 16u) P.v[q][1] = *(const GMEM u32x4a*)(sp + 16);
+          }
+        } else {
+          pay_load(P, pd, ps, pz);
+        }
 #pragma unroll
         for (int q = 0; q < kBkPay; ++q) {
           const uint32_t p = (uint32_t)(g + q) * kBkBlock + tid;
@@ -1934,7 +1956,39 @@ __global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
             if (o_poff) st_off(o_poff, out_cell0 + p, (int64_t)(out_byte0 + pb[q]), ow);
           }
         }
-        pay_store(P, pd, ps, pz);
+        if (staged) {
+          // the counters' LDS is free once the column scan is done: 2 KB per
+          // wave holds 64 payloads of up to 32 bytes
+          uint32_t* const stage = (uint32_t*)L.wc + w * (kWave * 8);
+#pragma unroll
+          for (int q = 0; q < kBkPay; ++q) {
+            const uint32_t p = (uint32_t)(g + q) * kBkBlock + tid;
+            const uint64_t act = ballot(p < len);  // a prefix of the wave's lanes
+            if (act == 0) continue;                // wave-uniform
+            const uint32_t last = 63u - (uint32_t)__clzll(act);
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pb[q]);
+            const uint32_t rel = pb[q] - b0;
+            const uint32_t tot =
+                (uint32_t)__builtin_amdgcn_readlane((int)(rel + pz[q]), (int)last);
+            const uint32_t nw = pz[q] >> 2;
+            const uint32_t v[8] = {P.v[q][0].x, P.v[q][0].y, P.v[q][0].z, P.v[q][0].w,
+                                   P.v[q][1].x, P.v[q][1].y, P.v[q][1].z, P.v[q][1].w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if ((uint32_t)j < nw) stage[(rel >> 2) + j] = v[j];
+            GMEM uint8_t* const dst = gm(o_pay + out_byte0 + b0);
+            for (uint32_t o = lane * 16u; o < tot; o += kWave * 16u) {
+              const uint32_t* sw = stage + (o >> 2);
+              if (o + 16u <= tot) {
+                *(GMEM u32x4a*)(dst + o) = u32x4a{sw[0], sw[1], sw[2], sw[3]};
+              } else {
+                for (uint32_t j = 0; j < ((tot - o) >> 2); ++j) ((GMEM uint32_t*)(dst + o))[j] = sw[j];
+              }
+            }
+          }
+        } else {
+          pay_store(P, pd, ps, pz);
+        }
       }
     }
     if (tid == 0) a.bucket_done[bk] = (take && fits) ? 1 : 0;

@@ -90,8 +90,8 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
 # A reading holds only for the kernel sources it was taken on; after any change
 # to them the traffic figure is reported as null.
 MEASURED_TRAFFIC = {
-    "step": {"sources_sha256": "a456f8d6f9eceddc890a10314e0481f294bbb842384ee36922348f1530dcb8a9",
-             "fetch_kib": 38016774.5, "write_kib": 45925645.4},
+    "step": {"sources_sha256": "cec032d990c2d494d24946db66fa3a5c17b483b43ba4c03fdcce7caee95b442b",
+             "fetch_kib": 38616930.2, "write_kib": 45638634.8},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
@@ -561,6 +561,21 @@ def bench_tune(args):
     print(json.dumps(res), flush=True)
 
 
+def stage_times(call, tplan, reps: int) -> dict:
+    """Mean device time of each stage of `reps` calls made with a timing plan
+    (the library records events around its launches on the call's stream);
+    keys are the stage name and its index within one call."""
+    acc = {}
+    for _ in range(reps):
+        call()
+        pi = {}
+        for name, v in tplan.stage_times():
+            k = pi.get(name, 0)
+            pi[name] = k + 1
+            acc.setdefault((name, k), []).append(v)
+    return {f"{n}{k}": float(np.mean(v)) for (n, k), v in acc.items()}
+
+
 def bench_hetero(args):
     """Heterogeneously balanced multigraph, partitioned (R = 256): 2^21 x 2^21,
     2^30 cells, 28-byte payload; every output array checked against the oracle."""
@@ -579,6 +594,12 @@ def bench_hetero(args):
     out = mgt.alloc_outputs(d, partitioned=True, payload_off=not fixed)
     ms = _timed(lambda: mgt.transpose(d, plan=plan, workspace=ws, partitioned=True, out=out),
                 args.steps, args.warmup)
+    tplan = mgt.plan_for(d, mgt.DEBUG_TIMING)
+    tws = ws if tplan.workspace_bytes <= ws.numel() else mgt.workspace_for(tplan, dev)
+    stages = stage_times(lambda: mgt.transpose(d, plan=tplan, workspace=tws, partitioned=True,
+                                               out=out), tplan, 3)
+    del tws
+    log(f"[hetero] stages (ms): {json.dumps({k: round(v, 3) for k, v in stages.items()})}")
     # every output array against the oracle's whole-matrix transpose (its
     # column-range mode over disjoint ranges in host threads) and partition counts
     torch.cuda.synchronize()
@@ -599,6 +620,7 @@ def bench_hetero(args):
            "mode": "hetero" + (" fixed-width" if fixed else ""),
            "value": a.nnz / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
            "hbm_frac_step": b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "bit_exact": ok,
+           "stages_ms": {k: round(v, 4) for k, v in stages.items()},
            "config": {"workload": "heterogeneous multigraph 2^21 x 2^21, 2^30 cells, 28-byte "
                                   "payload, R=256", "scale_shift": args.scale,
                       "nnz": a.nnz, "payload_bytes": a.payload_bytes}}
@@ -768,17 +790,7 @@ def main():
 
     # per-stage device times (events recorded by the library on the same stream)
     tplan = mgt.plan_for(d, mgt.DEBUG_TIMING)
-    acc = {}
-    n_t = max(3, min(args.steps, 5))
-    for _ in range(n_t):
-        step(tplan)
-        times = tplan.stage_times()
-        pi = {}
-        for name, v in times:
-            k = pi.get(name, 0)
-            pi[name] = k + 1
-            acc.setdefault((name, k), []).append(v)
-    stages = {f"{n}{k}": float(np.mean(v)) for (n, k), v in acc.items()}
+    stages = stage_times(lambda: step(tplan), tplan, max(3, min(args.steps, 5)))
     log(f"[bench] stages (ms): {json.dumps({k: round(v, 3) for k, v in stages.items()})}")
     n_passes = sum(1 for k in stages if k.rstrip("0123456789") == "scatter")
     packed = packs_records(a, False, n_passes) and not os.environ.get("MGT_NO_PACK")

@@ -101,8 +101,10 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
     call (template arguments as the library instantiates them)."""
     if stage == "hist":
         return "mgt::geo256::k_pass_hist"
+    if stage == "finishs":  # the 512-thread whole-bucket finish, two workgroups per CU
+        return "mgt::geo256::k_finish_bucket<512>"
     if stage == "finishb":
-        return "mgt::geo256::k_finish_bucket"
+        return "mgt::geo256::k_finish_bucket<1024>"
     if stage == "finish":
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
@@ -799,16 +801,20 @@ def main():
     kernels = {}
     for key, v in stages.items():
         st = key.rstrip("0123456789")
-        if st not in ("scatter", "finish", "finishb", "hist"):
+        if st not in ("scatter", "finish", "finishb", "finishs", "hist"):
             continue
         pidx = int(key[len(st):] or 0)
         name = profiler_kernel_name(st, pidx, n_passes, part)
         e = kernels.setdefault(name, [0.0, 0, 0])
         e[0] += v
-        # with the whole-bucket finish, k_finish only takes the buckets it left
-        # (none on this workload) and writes the tails
-        bytes_st = "finish" if st == "finishb" else st
-        if st == "finish" and "finishb0" in stages:
+        # the first whole-bucket launch takes the buckets (all of them on this
+        # workload); a later one and k_finish take what it left (none here),
+        # and k_finish writes the tails
+        first_b = "finishs0" if "finishs0" in stages else "finishb0"
+        bytes_st = st
+        if st in ("finishs", "finishb"):
+            bytes_st = "finish" if key == first_b else "tails"
+        if st == "finish" and first_b in stages:
             bytes_st = "tails"
         e[1] += kernel_bytes(a, bytes_st, pidx, False, n_passes, packed)
         e[2] += 1

@@ -17,6 +17,7 @@ constexpr int kSub = 2048;          // cells sorted in LDS at once
 constexpr int kWideBlock = 512;
 constexpr int kWideSub = 4096;
 constexpr int kMaxPassBits = 8;     // digit bits of a bits-mode pass (fan-out 256)
+constexpr int kMaxLastPassBits = 9; // the records-only pass in its 512-thread form (fan-out 512)
 constexpr int kScanBlock = 4096;    // elements per scan workgroup
 
 // Arguments of a partition pass (hist and scatter share them).
@@ -100,7 +101,11 @@ struct FinishArgs {
   uint8_t* bucket_done;       // [nbuckets] gathering finish with packed records: 1 where
                               // k_finish_bucket wrote the bucket (k_finish skips it), else 0;
                               // null: k_finish takes every bucket
-  uint32_t grid;              // k_finish_bucket: workgroups (one per CU)
+  uint32_t grid;              // k_finish_bucket: workgroups (one or two per CU)
+  uint32_t bk_threads;        // k_finish_bucket: 1024 (buckets up to 9,216 cells, one
+                              // workgroup per CU) or 512 (up to 4,608 cells, two per CU)
+  uint32_t skip_done;         // k_finish_bucket: leave buckets already marked 1 alone (a
+                              // 1,024-thread launch after a 512-thread one)
 };
 
 // Copies n bytes (a multiple of 4) from host memory to dst through kernel

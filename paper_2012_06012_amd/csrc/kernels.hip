@@ -14,13 +14,15 @@
 #include "prims.h"
 
 // Workgroup geometry of this copy of the device code. The library holds two:
-// 256 threads and 2,048-cell sub-chunks for every stage (this file), and 512
-// threads and 4,096-cell sub-chunks for the records-only pass alone
-// (kernels_wide.hip, which includes this file in a namespace of its own).
+// 256 threads, 2,048-cell sub-chunks and 8-bit passes for every stage (this
+// file), and 512 threads, 4,096-cell sub-chunks and up to 9-bit passes for the
+// records-only pass alone (kernels_wide.hip, which includes this file in a
+// namespace of its own).
 #ifndef MGT_GEO_NS
 #define MGT_GEO_NS geo256
 #define MGT_GEO_BLOCK ::mgt::kBlock
 #define MGT_GEO_SUB ::mgt::kSub
+#define MGT_GEO_FANBITS ::mgt::kMaxPassBits
 #endif
 
 namespace mgt {
@@ -564,7 +566,7 @@ struct SortLdsT {
   uint16_t wc[kFan * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
 };
 using SortLds = SortLdsT<kMaxFanout, true>;
-constexpr int kFanBits = 1 << kMaxPassBits;  // fan-out of a bits-mode pass
+constexpr int kFanBits = 1 << MGT_GEO_FANBITS;  // fan-out of a bits-mode pass
 
 // Ranks each lane's cells stably by digit (ballot multisplit per 64-cell
 // round, counters per (digit, wave)), scans the counters digit-major and
@@ -1692,27 +1694,37 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 // placed in LDS in output order, and written out in that order. Consecutive
 // output cells then go to consecutive addresses of t_col, t_payload_off and
 // t_payload (whole lines); only the payload reads are scattered, inside one
-// first-pass segment. One workgroup per CU walks the buckets in column order
+// first-pass segment. A persistent grid walks the buckets in column order
 // (all CUs on neighbouring buckets, so their payload sources share a segment
 // held in the memory-side cache). A bucket it does not take (more cells than
 // fit, payload sources spanning 2^32 bytes or more, 2^32 payload bytes or
 // more) is marked 0 in bucket_done and left to k_finish, which skips those
 // marked 1. A bucket of 2^7 columns of the large multigraph holds 8,192 cells
 // on average and at most 8,834, under kBkCap.
-constexpr int kBkBlock = 1024;
-constexpr int kBkNW = kBkBlock / kWave;
-constexpr int kBkItems = 9;                     // cells per lane
-constexpr int kBkCap = kBkBlock * kBkItems;     // cells of a bucket held at once
-constexpr int kBkWaveCells = kBkItems * kWave;  // contiguous cells of one wave
-constexpr int kBkPay = 2;                       // cells per lane whose payload is in flight
+constexpr int kBkItems = 9;  // cells per lane
+constexpr int kBkPay = 2;    // cells per lane whose payload is in flight
 
+// Two geometries: 1,024 threads (one workgroup per CU, buckets of up to 9,216
+// cells) and 512 threads (two workgroups per CU, up to 4,608 cells). With two
+// per CU, one workgroup's loads and LDS sort run while the other gathers, so
+// the CU keeps L2 misses in flight through every phase.
+template <int kBkBlock>
+struct BkGeo {
+  static constexpr int kNW = kBkBlock / kWave;
+  static constexpr int kCap = kBkBlock * kBkItems;     // cells of a bucket held at once
+  static constexpr int kWaveCells = kBkItems * kWave;  // contiguous cells of one wave
+};
+
+template <int kBkBlock>
 struct BucketLds {
+  static constexpr int kBkNW = BkGeo<kBkBlock>::kNW, kBkCap = BkGeo<kBkBlock>::kCap;
   uint32_t row[kBkCap];              // output order: original row id
   uint32_t src[kBkCap];              // output order: payload offset above the bucket's lowest
   uint32_t bp[kBkCap + 1];           // output order: size, then its exclusive prefix
   uint16_t wc[kFinishCols * kBkNW];  // (column, wave) counts, then their column-major scan
   uint64_t lo[kBkNW], hi[kBkNW], tot[kBkNW];
   uint32_t red[kBkNW + 1];
+  uint32_t next;                     // skip mode: the next bucket left by an earlier launch
 };
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
@@ -1738,14 +1750,16 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 }
 
 // A bucket k_finish_bucket can hold (block-uniform).
+template <int kBkBlock>
 __device__ __forceinline__ bool bucket_loadable(const Seg& s) {
-  return s.key_hi > s.key_lo && s.len > 0 && s.len <= (uint32_t)kBkCap;
+  return s.key_hi > s.key_lo && s.len > 0 && s.len <= (uint32_t)BkGeo<kBkBlock>::kCap;
 }
 
 // The bucket's 16-byte packed records, wave w holding cells
 // [w * kBkWaveCells, (w + 1) * kBkWaveCells) (clamped into the bucket).
 __device__ __forceinline__ void load_bucket(v4u (&r)[kBkItems], const uint32_t* rso, const Seg& s,
                                             uint32_t tid) {
+  constexpr int kBkWaveCells = kBkItems * kWave;
   const uint32_t w = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int q = 0; q < kBkItems; ++q) {
@@ -1759,8 +1773,12 @@ __device__ __forceinline__ void zero_bucket(v4u (&r)[kBkItems]) {
   for (int q = 0; q < kBkItems; ++q) r[q] = v4u{0u, 0u, 0u, 0u};
 }
 
-__global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
-  __shared__ BucketLds L;
+template <int kBkBlock>
+__global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
+  constexpr int kBkNW = BkGeo<kBkBlock>::kNW;
+  constexpr int kBkCap = BkGeo<kBkBlock>::kCap;
+  constexpr int kBkWaveCells = BkGeo<kBkBlock>::kWaveCells;
+  __shared__ BucketLds<kBkBlock> L;
   if (aborted(a.abort_flag) || !packed_records(a.pk_on, a.no_pack)) return;
   const uint32_t nb = a.nbuckets;
   uint32_t bk = blockIdx.x;
@@ -1768,6 +1786,26 @@ __global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
   const int ow = a.offset_width;
   Seg sg = a.buckets[bk];
   for (; bk < nb; bk += gridDim.x) {
+    if (a.skip_done) {
+      // this workgroup's next bucket that an earlier launch left (its flags
+      // read kBkBlock at a time), or none
+      for (;;) {
+        const uint32_t cand = bk + threadIdx.x * gridDim.x;
+        const bool left = cand < nb && !a.bucket_done[cand];
+        if (threadIdx.x == 0) L.next = ~0u;
+        __syncthreads();
+        if (left) atomicMin(&L.next, (uint32_t)threadIdx.x);
+        __syncthreads();
+        const uint32_t first = L.next;
+        __syncthreads();
+        const uint64_t nxt = first != ~0u ? (uint64_t)bk + (uint64_t)first * gridDim.x
+                                          : (uint64_t)bk + (uint64_t)kBkBlock * gridDim.x;
+        bk = nxt < nb ? (uint32_t)nxt : nb;
+        if (first != ~0u || bk >= nb) break;
+      }
+      if (bk >= nb) break;
+      sg = a.buckets[bk];
+    }
     // the thread index, opaque to the compiler inside each iteration: the
     // per-cell indexes derived from it are recomputed here instead of being
     // hoisted out of the loop (and spilled)
@@ -1777,7 +1815,7 @@ __global__ __launch_bounds__(kBkBlock, 1) void k_finish_bucket(FinishArgs a) {
     Seg sn = sg;
     if (bn < nb) sn = a.buckets[bn];
     v4u cur[kBkItems];
-    if (bucket_loadable(sg)) load_bucket(cur, a.rso_in, sg, tid);
+    if (bucket_loadable<kBkBlock>(sg)) load_bucket(cur, a.rso_in, sg, tid);
     else zero_bucket(cur);
     const ItemDev* it = &a.items[sg.item];
     const uint32_t nc = sg.key_hi - sg.key_lo;
@@ -2155,9 +2193,11 @@ hipError_t launch_children(const ChildArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_finish_bucket(const FinishArgs& a, hipStream_t s) {
-  if (a.nbuckets && a.bucket_done && a.grid)
-    hipLaunchKernelGGL(G::k_finish_bucket, dim3(a.grid < a.nbuckets ? a.grid : a.nbuckets),
-                       dim3(G::kBkBlock), 0, s, a);
+  if (a.nbuckets && a.bucket_done && a.grid) {
+    const dim3 g(a.grid < a.nbuckets ? a.grid : a.nbuckets);
+    if (a.bk_threads == 512) hipLaunchKernelGGL(G::k_finish_bucket<512>, g, dim3(512), 0, s, a);
+    else hipLaunchKernelGGL(G::k_finish_bucket<1024>, g, dim3(1024), 0, s, a);
+  }
   return hipGetLastError();
 }
 

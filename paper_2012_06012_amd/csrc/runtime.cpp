@@ -82,21 +82,26 @@ int env_cap(const char* name, int lo, int hi, int dflt) {
 int max_pass_bits() { return env_cap("MGT_MAX_PASS_BITS", 1, kMaxBitsPerPass, kMaxBitsPerPass); }
 int max_finish_bits() { return env_cap("MGT_MAX_FINISH_BITS", 0, kMaxFinishBits, kMaxFinishBits); }
 
-// Number of passes needed for `B` bits when the first pass may take `first_cap`
-// and every later one `mb`.
-int passes_for(int B, int first_cap, int mb) {
-  if (B <= 0) return 1;
-  int rest = B - std::min(B, first_cap);
-  return 1 + (rest + mb - 1) / mb;
+// Number of passes needed for `B` bits when the first pass may take
+// `first_cap`, the last of two or more `last_cap` and every other one `mb`.
+int passes_for(int B, int first_cap, int mb, int last_cap) {
+  if (B <= first_cap) return 1;
+  int L = 2, cap = first_cap + last_cap;
+  while (cap < B) {
+    ++L;
+    cap += mb;
+  }
+  return L;
 }
 
 // spread: a single-matrix call, whose finish buckets shrink (down to kSub / 8
 // cells) on small matrices so that about kTargetBuckets workgroups share the
 // finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
-// parallelism.
+// parallelism. last_cap: the bits the last pass of two or more may take (its
+// 512-thread form takes up to kMaxLastPassBits).
 Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
                     const int64_t* bounds, bool partitioned, int mb, int mf, bool spread,
-                    int force_fb = -1) {
+                    int force_fb, int last_cap) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -126,38 +131,69 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t 
   // Fewest passes first, then the smallest finish width that achieves them.
   int best_fb = fb_ideal, best_L = 1 << 30;
   for (int fb = fb_ideal; fb <= std::min(mf, K); ++fb) {
-    const int L = passes_for(K - fb, first_cap, mb);
+    const int L = passes_for(K - fb, first_cap, mb, last_cap);
     if (L < best_L) { best_L = L; best_fb = fb; }
   }
   if (K <= fb_ideal) { best_fb = K; best_L = 1; }
   if (force_fb >= 0) {  // a finish width set by the caller
     best_fb = std::min(force_fb, K);
-    best_L = passes_for(K - best_fb, first_cap, mb);
+    best_L = passes_for(K - best_fb, first_cap, mb, last_cap);
   }
   const int B = K - best_fb;
   s.finish_bits = best_fb;
   s.n_levels = best_L;
   int rest = B;
   s.bits[0] = std::min(B, first_cap);
-  if (!partitioned && best_L > 1) s.bits[0] = (B + best_L - 1) / best_L;  // spread evenly
+  if (!partitioned && best_L > 1)  // spread evenly, within the caps
+    s.bits[0] = std::min(first_cap, (B + best_L - 1) / best_L);
   rest -= s.bits[0];
   for (int l = 1; l < best_L; ++l) {
     const int left = best_L - l;
-    s.bits[l] = (rest + left - 1) / left;
+    const int cap = l == best_L - 1 ? last_cap : mb;
+    s.bits[l] = l == best_L - 1 ? rest : std::min(cap, (rest + left - 1) / left);
     rest -= s.bits[l];
   }
   return s;
 }
 
-Sched make_sched(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
-                 const int64_t* bounds, bool partitioned, bool spread, const Tune* t = nullptr) {
+uint32_t tile_cells_for(uint64_t nnz);
+
+// Column bits a finish bucket keeps when the last pass takes its extra bit.
+constexpr int kWideFinishMinBits = 5;
+
+// A single-matrix call whose tiles hold at least kWideSub cells runs its last
+// pass (records only) in the 512-thread form, which takes up to
+// kMaxLastPassBits bits when the pass cap is the full kMaxBitsPerPass.
+// The schedule a setting gives (it may need more than kMaxLevels passes).
+Sched make_sched_tuned(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
+                       const int64_t* bounds, bool partitioned, bool spread, const Tune* t) {
   const int mb = (t && t->pass_bits > 0) ? t->pass_bits : max_pass_bits();
   const int ff = (t && t->finish_bits >= 0) ? t->finish_bits : -1;
+  const uint32_t tile = (t && t->tile) ? t->tile : tile_cells_for((uint64_t)std::max<int64_t>(nnz, 0));
+  const bool wide = spread && tile >= (uint32_t)kWideSub;
+  const int last_cap = (wide && mb >= kMaxBitsPerPass) ? kMaxLastPassBits : mb;
   Sched s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, mb, max_finish_bits(),
-                          spread, ff);
-  if (s.n_levels > kMaxLevels)
+                          spread, ff, last_cap);
+  // A finish bucket of fewer than 2^kWideFinishMinBits columns carries the
+  // spread of single column degrees: on skewed inputs many such buckets
+  // outgrow the 512-thread finish. The extra last-pass bit is kept only when
+  // the buckets it buys span that many columns.
+  if (last_cap > mb && s.n_levels >= 2 && s.bits[s.n_levels - 1] > mb &&
+      s.finish_bits < kWideFinishMinBits)
+    s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, mb, max_finish_bits(),
+                      spread, ff, mb);
+  return s;
+}
+
+Sched make_sched(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
+                 const int64_t* bounds, bool partitioned, bool spread, const Tune* t = nullptr) {
+  Sched s = make_sched_tuned(n_cols, nnz, payload_bytes, R, bounds, partitioned, spread, t);
+  if (s.n_levels > kMaxLevels) {
+    const uint32_t tile = (t && t->tile) ? t->tile : tile_cells_for((uint64_t)std::max<int64_t>(nnz, 0));
+    const bool wide = spread && tile >= (uint32_t)kWideSub;
     s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, kMaxBitsPerPass,
-                      kMaxFinishBits, spread);
+                      kMaxFinishBits, spread, -1, wide ? kMaxLastPassBits : kMaxBitsPerPass);
+  }
   return s;
 }
 
@@ -433,6 +469,11 @@ void time_mark(mgt_plan_s* p, hipStream_t s, const char* name) {
 }
 
 // Compute units of the current device (read once per device).
+// Mean cells per finish bucket up to which the whole-bucket finish runs first
+// as two 512-thread workgroups per CU (capacity 4,608 cells), then as one
+// 1,024-thread workgroup per CU for the buckets that left (up to 9,216).
+constexpr uint64_t kBucketSmallMean = 4096;
+
 uint32_t device_cus() {
   static uint32_t cus[64] = {};
   int dev = 0;
@@ -697,11 +738,29 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
   f.pk_on = pk_on;
   f.no_pack = d_no_pack;
   if (pk_on && f.rso_in) {
-    // packed records: whole buckets first, the rest (and the tails) after
+    // packed records: whole buckets first, the rest (and the tails) after.
+    // Buckets of at most 4,096 cells on average go to the 512-thread form,
+    // two workgroups per CU (MGT_BUCKET_THREADS=512 or 1024 forces one).
     f.bucket_done = W + y.o_bdone;
-    f.grid = device_cus();
-    MGT_HIP(launch_finish_bucket(f, s));
-    time_mark(p, s, "finishb");
+    const uint64_t nb = std::max<uint64_t>(y.nseg[L], 1);
+    const bool small = y.total_nnz <= kBucketSmallMean * nb;
+    const int forced = env_cap("MGT_BUCKET_THREADS", 512, 1024, 0);
+    const bool run512 = forced ? forced == 512 : small;
+    const bool run1024 = forced ? forced == 1024 : true;
+    if (run512) {
+      f.bk_threads = 512;
+      f.skip_done = 0;
+      f.grid = 2 * device_cus();
+      MGT_HIP(launch_finish_bucket(f, s));
+      time_mark(p, s, "finishs");
+    }
+    if (run1024) {  // after the 512-thread launch: the buckets it left, up to 9,216 cells
+      f.bk_threads = 1024;
+      f.skip_done = run512 ? 1 : 0;
+      f.grid = device_cus();
+      MGT_HIP(launch_finish_bucket(f, s));
+      time_mark(p, s, "finishb");
+    }
   }
   MGT_HIP(launch_finish(f, s));
   time_mark(p, s, "finish");
@@ -1173,9 +1232,8 @@ int mgt_plan_set_schedule(mgt_plan_t plan, int32_t pass_bits, int32_t finish_bit
   }
   const mgt_desc& d = plan->desc;
   for (int part = 0; part < 2; ++part) {  // a setting that needs over kMaxLevels passes is refused
-    const Sched s = make_sched_mb(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, plan->bounds.data(),
-                                  part != 0, pass_bits > 0 ? pass_bits : max_pass_bits(),
-                                  max_finish_bits(), true, finish_bits);
+    const Sched s = make_sched_tuned(d.n_cols, d.nnz, d.payload_bytes, d.n_parts,
+                                     plan->bounds.data(), part != 0, true, &t);
     if (s.n_levels > kMaxLevels) return MGT_EUNSUPPORTED;
   }
   plan->tune = t;

@@ -269,15 +269,22 @@ def test_plan_schedule_settings():
     mgt = _lib()
     b = [i * (1 << 17) for i in range(65)]
     p = mgt.mgt_plan(1 << 23, 1 << 23, 1 << 29, 9663557316, 8, b)
-    assert p.schedule() == {"passes": 2, "bits": [8, 8], "finish_bits": 7, "tile_cells": 16384,
+    # the records-only pass of a single large matrix takes 9 bits (its 512-thread
+    # form), so two passes reach finish buckets of 2^6 columns, ~4,096 cells
+    assert p.schedule() == {"passes": 2, "bits": [8, 9], "finish_bits": 6, "tile_cells": 16384,
                             "partition_pass": False}
     # 64 partitions x 4: a fan-out of 256, whose segments hold 38 MB of payload on average
-    assert p.schedule(True)["partition_pass"] and p.schedule(True)["bits"] == [2, 8]
+    assert p.schedule(True)["partition_pass"] and p.schedule(True)["bits"] == [2, 9]
     # 30 GB over 256 partitions: 256 segments would average 117 MB, so the
     # partition pass takes a fan-out of 512 (256 x 2)
     h = mgt.mgt_plan(1 << 21, 1 << 21, 1 << 30, 28 << 30, 8, [i * (1 << 13) for i in range(257)])
+    # (a 9-bit last pass would leave finish buckets of 8 columns: kept at 8 bits)
     assert h.schedule(True) == {"passes": 2, "bits": [1, 8], "finish_bits": 4, "tile_cells": 16384,
                                 "partition_pass": True}
+    # tiles under 4,096 cells keep the last pass at 8 bits
+    p.set_schedule(8, -1, 2048)
+    assert p.schedule()["bits"] == [8, 8] and p.schedule()["finish_bits"] == 7
+    p.set_schedule()
     h2 = mgt.mgt_plan(1 << 21, 1 << 21, 1 << 30, 8 << 30, 8, [i * (1 << 13) for i in range(257)])
     assert h2.schedule(True)["bits"][0] == 0  # 8 GB: 256 segments of 32 MB
     ws0 = p.workspace_bytes
@@ -291,7 +298,7 @@ def test_plan_schedule_settings():
     assert p.schedule()["finish_bits"] == 9           # a refused setting changes nothing
     p.set_schedule(5, 8, 0)                            # 15 bits in passes of at most 5: three
     assert p.schedule()["passes"] == 3 and sum(p.schedule()["bits"]) == 15
-    assert p.set_schedule() == ws0 and p.schedule()["finish_bits"] == 7
+    assert p.set_schedule() == ws0 and p.schedule()["finish_bits"] == 6
     for bad in ((9, -1, 0), (-1, -1, 0), (0, 11, 0), (0, -2, 0), (0, -1, 1000), (0, -1, 32768)):
         with pytest.raises(mgt.MgtError):
             p.set_schedule(*bad)

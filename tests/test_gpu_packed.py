@@ -201,3 +201,48 @@ def test_hot_columns_packed(monkeypatch):
     a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz), fill_seed=5)
     assert (col == 777).sum() > 12288
     _check(a, False, 0, monkeypatch)
+
+
+@pytest.mark.parametrize("threads", [None, "512", "1024"])
+def test_whole_bucket_forms(threads, monkeypatch):
+    # packed buckets of every size class in one call: up to 4,608 cells (the
+    # 512-thread whole-bucket finish, two workgroups per CU), up to 9,216 (the
+    # 1,024-thread form, which runs after it and takes what it left) and more
+    # (k_finish). Unset: both forms in turn; "512" or "1024": that form alone.
+    if threads is not None:
+        monkeypatch.setenv("MGT_BUCKET_THREADS", threads)
+    rng = np.random.default_rng(43)
+    n_rows, n_cols = 40000, 1 << 16
+    deg = rng.poisson(2.0, size=n_rows) + 1
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
+    hot = rng.random(nnz)
+    col[hot < 0.06] = 1234                    # a bucket of 4,608 to 9,216 cells
+    col[(hot >= 0.06) & (hot < 0.17)] = 50000  # a bucket of more than 9,216
+    for i in range(n_rows):
+        col[rp[i]:rp[i + 1]].sort()
+    assert 4608 < (col == 1234).sum() <= 9216 - 200 and (col == 50000).sum() > 9216
+    a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz) * 4,
+                    fill_seed=7)
+    _check(a, False, 0, monkeypatch)
+
+
+@pytest.mark.parametrize("tile", [4096, 16384])
+def test_nine_bit_records_pass(tile):
+    # 2^23 columns with 6-bit finish buckets: 17 bits in two passes, the
+    # second (records only, 512-thread form) taking 9
+    from paper_2012_06012_amd import mgt
+    n = 1 << 23
+    a = gen.generate(1 << 16, n, seed=11, deg_law=gen.DEG_POISSON, deg_mean=64.0,
+                     col_law=gen.COL_UNIFORM, mult_law=gen.MULT_GEOMETRIC, pay_law=gen.PAY_FLOATS,
+                     w_lo=1, w_hi=8, offset_width=8, name="wide-columns")
+    d = to_device(a)
+    plan = mgt.plan_for(d, 0)
+    plan.set_schedule(8, 6, tile)
+    assert plan.schedule() == {"passes": 2, "bits": [8, 9], "finish_bits": 6, "tile_cells": tile,
+                               "partition_pass": False}
+    out, status = mgt.transpose(d, plan=plan)
+    assert int(status.cpu()[0]) == 0
+    assert_matches_oracle(a, host(out))

@@ -96,9 +96,12 @@ MEASURED_TRAFFIC = {
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
 
-def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: bool) -> str:
+def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: bool,
+                         packed: bool = False) -> str:
     """The profiler's name of the kernel behind a stage of one single-matrix
-    call (template arguments as the library instantiates them)."""
+    call (template arguments as the library instantiates them). A packed
+    records-only pass runs in the slim 512-thread kernel (the plain one
+    launched beside it returns at once)."""
     if stage == "hist":
         return "mgt::geo256::k_pass_hist"
     if stage == "finishs":  # the 512-thread whole-bucket finish, two workgroups per CU
@@ -109,10 +112,11 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
         if pass_idx == 0:
-            return "mgt::geo256::k_pass_scatter<true, false, false>"
+            return "mgt::geo256::k_pass_scatter<true, false, false, false>"
         if pass_idx == n_passes - 1:  # records only; 512-thread form for single matrices
-            return "mgt::geo512::k_pass_scatter<false, true, false>"
-        return "mgt::geo256::k_pass_scatter<false, false, false>"
+            return "mgt::geo512::k_pass_scatter<false, true, false, %s>" % (
+                "true" if packed else "false")
+        return "mgt::geo256::k_pass_scatter<false, false, false, false>"
     return stage
 
 
@@ -804,7 +808,7 @@ def main():
         if st not in ("scatter", "finish", "finishb", "finishs", "hist"):
             continue
         pidx = int(key[len(st):] or 0)
-        name = profiler_kernel_name(st, pidx, n_passes, part)
+        name = profiler_kernel_name(st, pidx, n_passes, part, packed)
         e = kernels.setdefault(name, [0.0, 0, 0])
         e[0] += v
         # the first whole-bucket launch takes the buckets (all of them on this

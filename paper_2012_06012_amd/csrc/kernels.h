@@ -63,6 +63,8 @@ struct PassArgs {
   int32_t pk_keys;            // with pk_on and no fixed-width item: the first histogram writes
                               // (column | size << s) per cell into rk_out, which the first pass
                               // reads instead of the columns and offsets
+  int32_t pk_split;           // set by the launcher: a slim packed-only kernel runs beside this
+                              // one and takes packed records (this one returns on them)
 };
 
 struct ChildArgs {

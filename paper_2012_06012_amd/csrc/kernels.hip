@@ -553,16 +553,21 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 
 // LDS state of one stable sub-chunk sort, for up to kFan digits. kBytes: the
 // sorted byte prefix (bpre) is kept, for passes that place payload bytes.
-template <int kFan, bool kBytes>
+// kSlim (packed records only, no byte prefix): key holds the whole packed
+// (column | size) word, and sizes, digits and cell indexes are not kept (the
+// digit is recomputed from the key), which leaves 12 bytes per cell.
+template <int kFan, bool kBytes, bool kSlim = false>
 struct SortLdsT {
+  static_assert(!(kSlim && kBytes), "the slim form keeps no byte prefix");
   static constexpr bool has_bytes = kBytes;
+  static constexpr bool slim = kSlim;
   uint32_t key[kSub];
-  uint32_t sz[kSub];
+  uint32_t sz[kSlim ? 1 : kSub];
   uint32_t row[kSub];
-  uint32_t idx[kSub];
+  uint32_t idx[kSlim ? 1 : kSub];
   uint32_t src[kSub];       // payload offset relative to the sub-chunk's first byte
   uint32_t bpre[kBytes ? kSub + 1 : 1];  // exclusive prefix of sz in sorted order; bpre[n] = total
-  uint16_t dig[kSub];
+  uint16_t dig[kSlim ? 1 : kSub];
   uint16_t wc[kFan * kNW];  // (digit, wave) counts, then their digit-major exclusive scan
 };
 using SortLds = SortLdsT<kMaxFanout, true>;
@@ -619,11 +624,11 @@ __device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t 
     if (i < n) {
       const uint32_t p = (uint32_t)L.wc[dg[r] * kNW + w] + rank[r];
       L.key[p] = key[r];
-      L.sz[p] = sz[r];
+      if constexpr (!LT::slim) L.sz[p] = sz[r];
       L.row[p] = row[r];
       if constexpr (kIdx) L.idx[p] = idx[r];
       L.src[p] = src[r];
-      L.dig[p] = (uint16_t)dg[r];
+      if constexpr (!LT::slim) L.dig[p] = (uint16_t)dg[r];
     }
   }
   __syncthreads();
@@ -1175,7 +1180,15 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
     }
-    sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
+    if constexpr (Lds::slim) {  // packed records-only pass: the whole (column | size) word
+      static_assert(kDefer && kPk, "the slim LDS form is for packed records-only passes");
+      uint32_t kw[kItems];
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) kw[r] = cur.a[r];
+      sort_sub<false>(L, F, dbits, n, kw, dg, sz, row, idx, src);
+    } else {
+      sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
+    }
 
     const uint8_t* src_base = pass0 ? i_pay + sub_base : a.pay_in + sub_base;
     bool xfer_per_cell = false;
@@ -1191,11 +1204,16 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       for (int r = 0; r < kItems; ++r) {
         const uint32_t i = r * kBlock + threadIdx.x;
         if (i < n) {
-          const uint32_t d = L.dig[i];
+          uint32_t d;
+          if constexpr (Lds::slim) d = digit_of(L.key[i] & pk_mask, sg, s_lb, s_ot, osh, R);
+          else d = L.dig[i];
           const uint64_t cd = seg_out + s_rc[d] + (i - L.wc[d * kNW]);
           const uint64_t so = sub_base + L.src[i];
           v4u rec;
-          if constexpr (kPk) {
+          if constexpr (Lds::slim) {
+            rec.x = L.key[i];
+            rec.y = L.row[i];
+          } else if constexpr (kPk) {
             rec.x = L.key[i] | (L.sz[i] << pk_shift);
             rec.y = L.row[i];
           } else {
@@ -1297,10 +1315,16 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 // on a CU instead of two.
 // kVal (first pass only): every cell carries a value of its own (item vval)
 // in place of its row id, so no rows are expanded.
-template <bool kPass0, bool kDefer, bool kVal>
-__global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scatter(PassArgs a) {
+// kSlim (the 512-thread records-only pass): packed records only, in the slim
+// LDS form (about 58 KB), two workgroups per CU; it leaves a call whose
+// records could not be packed to the plain kernel launched beside it, which
+// in turn leaves packed calls to it (pk_split).
+template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false>
+__global__ __launch_bounds__(kBlock, kSlim ? 2048 / kBlock : (kDefer ? 768 / kBlock : 2))
+void k_pass_scatter(PassArgs a) {
+  static_assert(!kSlim || (kDefer && !kPass0 && !kVal), "slim: the records-only pass");
   constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
-  __shared__ SortLdsT<kFan, !kDefer> L;
+  __shared__ SortLdsT<kFan, !kDefer, kSlim> L;
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
   __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
   __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
@@ -1309,8 +1333,15 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   __shared__ uint32_t s_si, s_extra;
   __shared__ uint32_t s_red[kNW + 1];
   if (aborted(a.abort_flag)) return;
+  if constexpr (kSlim) {
+    if (packed_records(a.pk_on, a.no_pack))
+      scatter_body<false, true, false, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                    s_extra, s_red);
+    return;
+  } else {
   if constexpr (!kVal && kPass0 != kDefer) {
     if (packed_records(a.pk_on, a.no_pack)) {
+      if (a.pk_split) return;  // the slim kernel takes it
       if (kPass0 && a.pk_keys)
         scatter_body<kPass0, kDefer, kVal, true, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
                                                        s_extra, s_red);
@@ -1322,6 +1353,7 @@ __global__ __launch_bounds__(kBlock, kDefer ? 768 / kBlock : 2) void k_pass_scat
   }
   scatter_body<kPass0, kDefer, kVal, false, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
                                                    s_extra, s_red);
+  }
 }
 
 // (the 512-thread copy of this file needs only the records-only scatter)
@@ -2109,9 +2141,16 @@ static inline dim3 grid1(uint64_t n) { return dim3((unsigned)n); }
 
 #ifdef MGT_WIDE
 hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s) {
-  if (a.g8)
+  if (a.g8) {
+    PassArgs b = a;
+    if (a.pk_on) {  // packed records in the slim form; the plain kernel takes the rest
+      b.pk_split = 1;
+      hipLaunchKernelGGL((G::k_pass_scatter<false, true, false, true>), grid1(a.g8), dim3(G::kBlock),
+                         0, s, b);
+    }
     hipLaunchKernelGGL((G::k_pass_scatter<false, true, false>), grid1(a.g8), dim3(G::kBlock), 0, s,
-                       a);
+                       b);
+  }
   return hipGetLastError();
 }
 #else

@@ -517,6 +517,14 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
   uint8_t* W = (uint8_t*)ws;
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
+  // Every later pass fits the LDS of the kernel that will run it: 9 bits only
+  // in the last pass of a single-matrix call run in the 512-thread form.
+  const bool wide_last = n == 1 && y.L >= 2 && y.tile_cells >= (uint32_t)kWideSub;
+  for (uint32_t i = 0; i < n; ++i)
+    for (int l = 1; l < items[i].s.n_levels; ++l) {
+      const int cap = (l == y.L - 1 && wide_last) ? kMaxLastPassBits : kMaxPassBits;
+      if (items[i].s.bits[l] > cap) return MGT_EINVAL;
+    }
   // Packed records (see PassArgs): one records-only pass, no perm, not a view
   // operation, at most 28 column bits in every item. The first histogram
   // falls back to the wide records if any payload size does not fit.

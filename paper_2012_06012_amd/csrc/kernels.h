@@ -65,6 +65,10 @@ struct PassArgs {
                               // reads instead of the columns and offsets
   int32_t pk_split;           // set by the launcher: a slim packed-only kernel runs beside this
                               // one and takes packed records (this one returns on them)
+  int32_t rec12;              // the slim kernel writes 12-byte packed records (column | size,
+                              // row, payload offset minus the finish bucket's first byte as a
+                              // signed 32-bit word) unless *big_seg is set
+  const int32_t* big_seg;
 };
 
 struct ChildArgs {
@@ -81,6 +85,8 @@ struct ChildArgs {
   uint32_t* child_hsize;
   uint32_t tile_cells;
   const int32_t* abort_flag;
+  int32_t* big_seg;           // non-null where the children are the last pass's input
+                              // segments: set to 1 if one holds 2^31 payload bytes or more
 };
 
 struct FinishArgs {
@@ -108,6 +114,8 @@ struct FinishArgs {
                               // workgroup per CU) or 512 (up to 4,608 cells, two per CU)
   uint32_t skip_done;         // k_finish_bucket: leave buckets already marked 1 alone (a
                               // 1,024-thread launch after a 512-thread one)
+  int32_t rec12;              // packed records are 12 bytes (see PassArgs) unless *big_seg
+  const int32_t* big_seg;
 };
 
 // Copies n bytes (a multiple of 4) from host memory to dst through kernel

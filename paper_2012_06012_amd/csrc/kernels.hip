@@ -782,6 +782,11 @@ constexpr int kPay = 4;  // cells per lane whose payload words are held at once
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // 16-byte aligned record
 typedef uint32_t u32x2a __attribute__((ext_vector_type(2), aligned(4)));
+// A 12-byte packed record (a three-element vector type would be padded to 16).
+struct alignas(4) Rec12 {
+  uint32_t x, y, z;
+};
+static_assert(sizeof(Rec12) == 12, "12-byte record");
 template <int N>
 struct PayRegsT {
   u32x4a v[N][2];
@@ -971,14 +976,26 @@ __device__ __forceinline__ void load_sub_pk8(SubLoad& S, const uint2* ks, uint64
     S.a[r] = x.x; S.c[r] = x.y;
   }
 }
+// rec12: 12-byte records whose third word is the payload offset minus the
+// bucket's first byte `byte0`, as a signed 32-bit value.
 __device__ __forceinline__ void load_sub_pk16(SubLoad& S, const uint32_t* rso, uint64_t pos0,
-                                              uint32_t n) {
+                                              uint32_t n, bool rec12, uint64_t byte0) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+  if (rec12) {
 #pragma unroll
-  for (int r = 0; r < kItems; ++r) {
-    const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
-    const v4u y = gm((const v4u*)rso)[pos0 + i];
-    S.a[r] = y.x; S.c[r] = y.y; S.e[r] = y.z; S.f[r] = y.w;
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
+      const GMEM Rec12* const y = gm((const Rec12*)rso) + pos0 + i;
+      const uint64_t off = byte0 + (uint64_t)(int64_t)(int32_t)y->z;
+      S.a[r] = y->x; S.c[r] = y->y; S.e[r] = (uint32_t)off; S.f[r] = (uint32_t)(off >> 32);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
+      const v4u y = gm((const v4u*)rso)[pos0 + i];
+      S.a[r] = y.x; S.c[r] = y.y; S.e[r] = y.z; S.f[r] = y.w;
+    }
   }
 }
 constexpr int kFieldsPk8 = 1 | 4;
@@ -1076,9 +1093,14 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   if constexpr (kPass0)
     if (sg.mode)
       for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
+  // 12-byte packed records (slim records-only pass): each cell's payload
+  // offset is stored relative to the first byte of the finish bucket it
+  // lands in, digit d's child, kept in s_rb (block-uniform choice)
+  const bool rec12 = Lds::slim && a.rec12 && *(volatile const int32_t*)a.big_seg == 0;
   for (uint32_t d = threadIdx.x; d < F; d += kBlock) {
     s_rc[d] = (uint32_t)(a.ocnt[hb + (uint64_t)d * nt + j] - seg_out);
     if constexpr (!kDefer) s_rb[d] = a.obyt[hb + (uint64_t)d * nt + j];
+    else if constexpr (Lds::slim) s_rb[d] = a.obyt[hb + (uint64_t)d * nt];
   }
   uint32_t r0 = 0;
   RowPf rpf{0, 0}, rpf_next{0, 0};
@@ -1211,6 +1233,14 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
           const uint64_t so = sub_base + L.src[i];
           v4u rec;
           if constexpr (Lds::slim) {
+            if (rec12) {
+              const uint32_t rel = (uint32_t)(so - s_rb[d]);  // |so - byte0| < 2^31
+              GMEM Rec12* const q = gm((Rec12*)a.rso_out) + cd;
+              q->x = L.key[i];
+              q->y = L.row[i];
+              q->z = rel;
+              continue;
+            }
             rec.x = L.key[i];
             rec.y = L.row[i];
           } else if constexpr (kPk) {
@@ -1326,7 +1356,8 @@ void k_pass_scatter(PassArgs a) {
   constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
   __shared__ SortLdsT<kFan, !kDefer, kSlim> L;
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
-  __shared__ uint64_t s_rb[kDefer ? 1 : kFan];          // running destination byte per digit
+  __shared__ uint64_t s_rb[kDefer && !kSlim ? 1 : kFan];  // running destination byte per digit
+                                                          // (slim: each child's first byte)
   __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
   __shared__ uint16_t s_ot[kPass0 ? kOwnerT + 1 : 1];   // their coarse owner table
   __shared__ Seg s_seg;
@@ -1509,6 +1540,8 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
                                             uint64_t* s_cb, uint32_t* s_red, uint64_t* s_red64) {
   constexpr int kFields = kGather ? (kPk ? kFieldsPk16 : kFieldsRecSo) : kFieldsRec;
   const uint32_t* const so = kGather ? a.rso_in : nullptr;
+  // packed records of 12 bytes (block-uniform; see PassArgs::rec12)
+  const bool rec12 = kPk && a.rec12 && *(volatile const int32_t*)a.big_seg == 0;
   const uint64_t bk = kGather ? (uint64_t)blockIdx.x : xcd_tile(blockIdx.x, a.g8);
   if (bk >= a.nbuckets) return;
   const Seg sg = a.buckets[bk];
@@ -1544,7 +1577,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
       for (int q = 0; q < kBatch; ++q) {
         const uint64_t e = sg.cell0 + min(c + q * kBlock, len - 1);
         if constexpr (kPk) {
-          const uint32_t x = gm(so)[4 * e];
+          const uint32_t x = gm(so)[(rec12 ? 3u : 4u) * e];
           ks[q] = make_uint2(x & pk_mask, x >> pk_shift);
         } else {
           ks[q] = a.ks_in[e];
@@ -1586,7 +1619,7 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
   uint64_t src_sub = sg.byte0;  // level-buffer byte of the current sub-chunk's first cell
   SubLoad cur, nxt;
   if (len) {
-    if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0, min((uint32_t)kSub, len));
+    if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0, min((uint32_t)kSub, len), rec12, sg.byte0);
     else load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0, min((uint32_t)kSub, len));
     settle<kFields>(cur, nxt);
   }
@@ -1620,7 +1653,8 @@ __device__ __forceinline__ void finish_body(const FinishArgs& a, SortLds& L, uin
     }
     // next sub-chunk's loads, issued after this one's registers were read
     if (c1 < len) {
-      if constexpr (kPk) load_sub_pk16(nxt, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
+      if constexpr (kPk)
+        load_sub_pk16(nxt, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1), rec12, sg.byte0);
       else load_sub_rec(nxt, a.ks_in, a.rk_in, so, sg.cell0 + c1, min((uint32_t)kSub, len - c1));
     }
     sort_sub<!kPk>(L, nc, dbits, n, key, dg, sz, row, idx, src);
@@ -1787,16 +1821,28 @@ __device__ __forceinline__ bool bucket_loadable(const Seg& s) {
   return s.key_hi > s.key_lo && s.len > 0 && s.len <= (uint32_t)BkGeo<kBkBlock>::kCap;
 }
 
-// The bucket's 16-byte packed records, wave w holding cells
-// [w * kBkWaveCells, (w + 1) * kBkWaveCells) (clamped into the bucket).
+// The bucket's packed records, wave w holding cells
+// [w * kBkWaveCells, (w + 1) * kBkWaveCells) (clamped into the bucket), each
+// as (column | size, row, payload offset low and high words). rec12: the
+// records are 12 bytes, the offset stored relative to the bucket's first byte.
 __device__ __forceinline__ void load_bucket(v4u (&r)[kBkItems], const uint32_t* rso, const Seg& s,
-                                            uint32_t tid) {
+                                            uint32_t tid, bool rec12) {
   constexpr int kBkWaveCells = kBkItems * kWave;
   const uint32_t w = tid / kWave, lane = tid % kWave;
+  if (rec12) {
 #pragma unroll
-  for (int q = 0; q < kBkItems; ++q) {
-    const uint32_t i = min(w * kBkWaveCells + q * kWave + lane, s.len - 1);
-    r[q] = gm((const v4u*)rso)[s.cell0 + i];
+    for (int q = 0; q < kBkItems; ++q) {
+      const uint32_t i = min(w * kBkWaveCells + q * kWave + lane, s.len - 1);
+      const GMEM Rec12* const t = gm((const Rec12*)rso) + s.cell0 + i;
+      const uint64_t off = s.byte0 + (uint64_t)(int64_t)(int32_t)t->z;
+      r[q] = v4u{t->x, t->y, (uint32_t)off, (uint32_t)(off >> 32)};
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < kBkItems; ++q) {
+      const uint32_t i = min(w * kBkWaveCells + q * kWave + lane, s.len - 1);
+      r[q] = gm((const v4u*)rso)[s.cell0 + i];
+    }
   }
 }
 
@@ -1812,6 +1858,7 @@ __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
   constexpr int kBkWaveCells = BkGeo<kBkBlock>::kWaveCells;
   __shared__ BucketLds<kBkBlock> L;
   if (aborted(a.abort_flag) || !packed_records(a.pk_on, a.no_pack)) return;
+  const bool rec12 = a.rec12 && *(volatile const int32_t*)a.big_seg == 0;  // block-uniform
   const uint32_t nb = a.nbuckets;
   uint32_t bk = blockIdx.x;
   if (bk >= nb) return;
@@ -1847,7 +1894,7 @@ __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
     Seg sn = sg;
     if (bn < nb) sn = a.buckets[bn];
     v4u cur[kBkItems];
-    if (bucket_loadable<kBkBlock>(sg)) load_bucket(cur, a.rso_in, sg, tid);
+    if (bucket_loadable<kBkBlock>(sg)) load_bucket(cur, a.rso_in, sg, tid, rec12);
     else zero_bucket(cur);
     const ItemDev* it = &a.items[sg.item];
     const uint32_t nc = sg.key_hi - sg.key_lo;
@@ -2118,7 +2165,7 @@ __global__ __launch_bounds__(kBlock) void k_children(ChildArgs a) {
     ch.shift = rb >= nbits ? rb - nbits : 0u;
     ch.mode = 0;
     ch.pad = 0;
-    (void)b1;
+    if (a.big_seg && b1 - b0 >= (1ull << 31)) *a.big_seg = 1;  // 12-byte records cannot reach
     a.children[cbase + d] = ch;
     if (a.child_tiles) {
       const uint32_t tiles = (uint32_t)((ch.len + a.tile_cells - 1) / a.tile_cells);

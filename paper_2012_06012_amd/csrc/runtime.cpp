@@ -660,6 +660,9 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
 
   const int L = y.L;
   int32_t* d_no_pack = d_abort + 4;  // in the uploaded (zeroed) abort block
+  int32_t* d_big_seg = d_abort + 5;  // likewise: a last-pass input segment of >= 2^31 bytes
+  // 12-byte packed records where the slim records-only kernel runs
+  const int32_t rec12 = (pk_on && wide_last) ? 1 : 0;
   // key words from the first histogram pay only where the first pass would
   // otherwise read payload offsets (fixed-width items read columns only)
   int32_t pk_keys = pk_on;
@@ -701,6 +704,8 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
     a.pk_on = pk_on;
     a.no_pack = d_no_pack;
     a.pk_keys = pk_keys;
+    a.rec12 = (l == L - 1) ? rec12 : 0;
+    a.big_seg = d_big_seg;
     MGT_HIP(launch_pass_hist(a, s));
     time_mark(p, s, "hist");
     const uint64_t nseg = y.nseg[l];
@@ -720,6 +725,7 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
     c.child_hsize = (l + 1 < L) ? hsz(l + 1) : nullptr;
     c.tile_cells = y.tile_cells;
     c.abort_flag = d_abort;
+    c.big_seg = (rec12 && l + 2 == L) ? d_big_seg : nullptr;
     MGT_HIP(launch_children(c, s));
     if (l + 1 < L)
       MGT_HIP(launch_scan(tcnt(l + 1), tstart(l + 1), hsz(l + 1), hstart(l + 1), nullptr, y.nseg[l + 1], scan, s));
@@ -745,6 +751,8 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
   f.g8 = align_up(y.nseg[L], 8);
   f.pk_on = pk_on;
   f.no_pack = d_no_pack;
+  f.rec12 = rec12;
+  f.big_seg = d_big_seg;
   if (pk_on && f.rso_in) {
     // packed records: whole buckets first, the rest (and the tails) after.
     // Buckets of at most 4,096 cells on average go to the 512-thread form,

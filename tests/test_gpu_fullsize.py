@@ -146,3 +146,29 @@ def test_payload_offsets_above_4g():
     del out, d, ref, pc, a
     gc.collect()
     torch.cuda.empty_cache()
+
+
+def test_last_pass_segment_over_2g():
+    """Packed records of a single large matrix are 12 bytes, the payload offset
+    stored relative to the finish bucket's first byte in 32 bits. Here every
+    cell lies in one first-pass segment of about 2.3 GB (2^24 columns, all
+    cells in the lowest 2^16), too wide for that, so the call keeps 16-byte
+    records; compared in full with the oracle."""
+    from paper_2012_06012_amd import mgt
+    n_rows, n_cols, deg = 1 << 20, 1 << 24, 32
+    rng = np.random.default_rng(23)
+    rp = np.arange(n_rows + 1, dtype=np.int64) * deg
+    col = np.sort(rng.integers(0, 1 << 16, size=(n_rows, deg)), axis=1).astype(np.int32).ravel()
+    widths = np.full(col.shape[0], 68, dtype=np.int64)
+    a = gen.from_arrays(n_rows, n_cols, rp, col, widths=widths, fill_seed=23)
+    assert a.payload_bytes >= 2**31, a.payload_bytes
+    d = to_device(a)
+    sc = mgt.plan_for(d, 0).schedule()
+    assert sc["passes"] == 2 and sc["tile_cells"] >= 4096, sc  # the 12-byte record path
+    _log(f"[fullsize] >2G segment: {a.nnz} cells, {a.payload_bytes} payload bytes, {sc}")
+    ref = oracle.transpose_sliced(a, slices=2 * oracle.host_threads())
+    out = _run(d, partitioned=False, perm=False, what=">2G segment")
+    compare_full(out, ref, what=">2G segment")
+    del out, d, ref, a
+    gc.collect()
+    torch.cuda.empty_cache()

@@ -246,3 +246,31 @@ def test_nine_bit_records_pass(tile):
     out, status = mgt.transpose(d, plan=plan)
     assert int(status.cpu()[0]) == 0
     assert_matches_oracle(a, host(out))
+
+
+@pytest.mark.parametrize("threads", [None, "512", "1024"])
+def test_twelve_byte_records_all_finish_forms(threads, monkeypatch):
+    # a single matrix whose tiles hold 4,096 cells or more: its records-only
+    # pass runs in the slim form and writes 12-byte records (payload offset
+    # relative to the finish bucket's first byte), read back by every finish
+    # path: buckets of up to 4,608 cells, up to 9,216, and more (k_finish)
+    if threads is not None:
+        monkeypatch.setenv("MGT_BUCKET_THREADS", threads)
+    rng = np.random.default_rng(47)
+    n_rows, n_cols = 200000, 1 << 16
+    deg = rng.poisson(20.0, size=n_rows) + 1
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
+    hot = rng.random(nnz)
+    col[hot < 0.0017] = 1234
+    col[(hot >= 0.0017) & (hot < 0.0047)] = 50000
+    for i in range(n_rows):
+        col[rp[i]:rp[i + 1]].sort()
+    assert 4608 < (col == 1234).sum() <= 9000 and (col == 50000).sum() > 9216
+    a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz) * 4,
+                    fill_seed=9)
+    from paper_2012_06012_amd import mgt
+    assert mgt.plan_for(to_device(a), 0).schedule()["tile_cells"] >= 4096
+    _check(a, False, 0, monkeypatch)

@@ -131,13 +131,14 @@ def test_size_too_wide_to_pack_falls_back(monkeypatch):
         _check(a, False, 0, monkeypatch)
 
 
-def test_graph_replays_packed():
+@pytest.mark.parametrize("tile", [0, 4096])  # 4,096: the slim pass and 12-byte records
+def test_graph_replays_packed(tile):
     # a recorded packed call: replays after the inputs change in place
     from paper_2012_06012_amd import mgt
     a = gen.random_small(21, n_rows=5000, n_cols=6000, deg_mean=6.0, w_lo=0, w_hi=17)
     d = to_device(a)
     plan = mgt.plan_for(d, 0)
-    plan.set_schedule(*_two_pass(a, False), 0)
+    plan.set_schedule(*_two_pass(a, False, tile), tile)
     assert plan.schedule(False)["passes"] == 2
     g, out, status = mgt.transpose_graph(d, plan=plan)
     for k in range(3):

@@ -59,14 +59,16 @@ def _check(a, d, plan, partitioned, perm):
         assert np.array_equal(out["perm"].cpu().numpy().view(np.uint32), t.perm)
 
 
-@pytest.mark.parametrize("sched", [None, (5, 4, 0), (4, 3, 0)], ids=["rule", "2pass", "3pass"])
+@pytest.mark.parametrize("sched", [None, (5, 4, 0), (4, 3, 0), (8, 4, 4096)],
+                         ids=["rule", "2pass", "3pass", "slim12"])
 @pytest.mark.parametrize("partitioned", [False, True], ids=["plain", "part"])
 @pytest.mark.parametrize("perm", [False, True], ids=["noperm", "perm"])
 def test_noalloc_equals_workspace_call(sched, partitioned, perm):
     from paper_2012_06012_amd import mgt
     # 2^14 x 2^14 with 2^20 cells (2^13 x 2^13 with 2^19 cells for three passes,
     # whose workspace is larger), R = 64; then 1,000 x 1,000 with about 2e4
-    # cells, R = 4
+    # cells, R = 4. slim12: 4,096-cell tiles, so the records-only pass runs in
+    # its slim form and, without perm, writes 12-byte records
     big = gen.large(seed=1, scale=10 if sched == (4, 3, 0) else 9)
     small = gen.tiny(seed=2)
     for a in (big, small):             # the second call is the smaller one

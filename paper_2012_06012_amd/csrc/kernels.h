@@ -65,6 +65,8 @@ struct PassArgs {
                               // reads instead of the columns and offsets
   int32_t pk_split;           // set by the launcher: a slim packed-only kernel runs beside this
                               // one and takes packed records (this one returns on them)
+  int32_t slim0;              // first pass of a call whose items are all split by column bits
+                              // (no partitions): packed records go to the slim first pass
   int32_t rec12;              // the slim kernel writes 12-byte packed records (column | size,
                               // row, payload offset minus the finish bucket's first byte as a
                               // signed 32-bit word) unless *big_seg is set
@@ -152,6 +154,7 @@ hipError_t launch_view_keys(const ViewArgs& a, hipStream_t s);
 hipError_t launch_pass_hist(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s);
 hipError_t launch_pass_scatter_wide(const PassArgs& a, hipStream_t s);  // records-only pass
+hipError_t launch_pass0_slim(const PassArgs& a, hipStream_t s);         // packed first pass (slim)
 hipError_t launch_children(const ChildArgs& a, hipStream_t s);
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 // Whole-bucket finish of a gathering call with packed records (runs before

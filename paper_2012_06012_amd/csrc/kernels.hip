@@ -195,13 +195,15 @@ __device__ __forceinline__ uint32_t owner_lut(const int32_t* lb, const uint16_t*
 // (key - key_lo) below `shift`. Partition mode (pass 1 of a partitioned
 // matrix): the destination partition, then the top `bits` bits of the column
 // inside it. Out-of-range keys (invalid input) are clamped into the fan-out.
+__device__ __forceinline__ uint32_t digit_bits(uint32_t key, const Seg& s) {
+  const uint32_t m = (1u << s.bits) - 1u;
+  const uint32_t d = (key - s.key_lo) >> s.shift;
+  return d > m ? m : d;
+}
 __device__ __forceinline__ uint32_t digit_of(uint32_t key, const Seg& s, const int32_t* lb,
                                              const uint16_t* ot, int osh, uint32_t R) {
+  if (s.mode == 0) return digit_bits(key, s);
   const uint32_t m = (1u << s.bits) - 1u;
-  if (s.mode == 0) {
-    const uint32_t d = (key - s.key_lo) >> s.shift;
-    return d > m ? m : d;
-  }
   const uint32_t p = owner_lut(lb, ot, osh, R, (int64_t)key);
   const int64_t rel = (int64_t)key - lb[p];
   uint32_t sub = rel < 0 ? 0u : (uint32_t)(rel >> s.shift);
@@ -553,12 +555,12 @@ __global__ __launch_bounds__(kBlock) void k_pass_hist(PassArgs a) {
 
 // LDS state of one stable sub-chunk sort, for up to kFan digits. kBytes: the
 // sorted byte prefix (bpre) is kept, for passes that place payload bytes.
-// kSlim (packed records only, no byte prefix): key holds the whole packed
-// (column | size) word, and sizes, digits and cell indexes are not kept (the
-// digit is recomputed from the key), which leaves 12 bytes per cell.
+// kSlim (packed records only): key holds the whole packed (column | size)
+// word, and sizes, digits and cell indexes are not kept (the size and digit
+// are recomputed from the key), which leaves 12 bytes per cell, 16 with the
+// byte prefix.
 template <int kFan, bool kBytes, bool kSlim = false>
 struct SortLdsT {
-  static_assert(!(kSlim && kBytes), "the slim form keeps no byte prefix");
   static constexpr bool has_bytes = kBytes;
   static constexpr bool slim = kSlim;
   uint32_t key[kSub];
@@ -577,12 +579,14 @@ constexpr int kFanBits = 1 << MGT_GEO_FANBITS;  // fan-out of a bits-mode pass
 // round, counters per (digit, wave)), scans the counters digit-major and
 // stores the cells in sorted order. Registers hold kItems cells per lane in
 // wave order (cell i = wave*kWaveCells + r*64 + lane). Ends with a barrier.
-// kIdx: the cell index travels (only perm needs it).
+// kIdx: the cell index travels (only perm needs it). szsh: in the slim form
+// with a byte prefix, a cell's size is its key word shifted right by szsh.
 template <bool kIdx = true, class LT>
 __device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t n,
                                          const uint32_t (&key)[kItems], const uint32_t (&dg)[kItems],
                                          const uint32_t (&sz)[kItems], const uint32_t (&row)[kItems],
-                                         const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems]) {
+                                         const uint32_t (&idx)[kItems], const uint32_t (&src)[kItems],
+                                         int szsh = 0) {
   const uint32_t w = threadIdx.x / kWave, lane = lane_id();
   const uint32_t E = F * kNW;
   for (uint32_t e = threadIdx.x; e < E; e += kBlock) L.wc[e] = 0;
@@ -639,7 +643,8 @@ __device__ __forceinline__ void sort_sub(LT& L, uint32_t F, int dbits, uint32_t 
     uint32_t s = 0;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      v[q] = (p0 + q < n) ? L.sz[p0 + q] : 0u;
+      if constexpr (LT::slim) v[q] = (p0 + q < n) ? L.key[p0 + q] >> szsh : 0u;
+      else v[q] = (p0 + q < n) ? L.sz[p0 + q] : 0u;
       s += v[q];
     }
     __shared__ uint32_t red2[kNW + 1];
@@ -914,8 +919,8 @@ __device__ __forceinline__ void settle(SubLoad& dst, const SubLoad& src) {
 // for them. val: per-cell carried values (view operations), into d.
 __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, const void* poff,
                                                uint64_t kfirst, uint32_t n, int lg, int32_t fw,
-                                               const uint32_t* val) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+                                               const uint32_t* val, uint32_t tid = threadIdx.x) {
+  const uint32_t w = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
@@ -947,8 +952,9 @@ __device__ __forceinline__ void load_sub_pass0(SubLoad& S, const int32_t* col, c
 }
 
 __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const uint2* rk,
-                                             const uint32_t* rso, uint64_t pos0, uint32_t n) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+                                             const uint32_t* rso, uint64_t pos0, uint32_t n,
+                                             uint32_t tid = threadIdx.x) {
+  const uint32_t w = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
@@ -967,8 +973,9 @@ __device__ __forceinline__ void load_sub_rec(SubLoad& S, const uint2* ks, const 
 // Packed records (a single matrix with one records-only pass, no perm): after
 // the first pass a cell is (column | size << pk_shift, row), after the second
 // (column | size << pk_shift, row, payload offset as two words).
-__device__ __forceinline__ void load_sub_pk8(SubLoad& S, const uint2* ks, uint64_t pos0, uint32_t n) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+__device__ __forceinline__ void load_sub_pk8(SubLoad& S, const uint2* ks, uint64_t pos0, uint32_t n,
+                                             uint32_t tid = threadIdx.x) {
+  const uint32_t w = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = min(w * kWaveCells + r * kWave + lane, n - 1);
@@ -1005,8 +1012,9 @@ constexpr int kFieldsPk8 = 1 | 4;
 // first cell (item-local index kfirst) from the offsets or the fixed width.
 __device__ __forceinline__ void load_sub_pk4(SubLoad& S, const uint32_t* pk4, const void* poff,
                                              uint64_t kfirst, uint64_t lfirst, uint32_t n, int lg,
-                                             int32_t fw) {
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
+                                             int32_t fw,
+                                             uint32_t tid = threadIdx.x) {
+  const uint32_t w = tid / kWave, lane = tid % kWave;
 #pragma unroll
   for (int r = 0; r < kItems; ++r) {
     const uint32_t i = w * kWaveCells + r * kWave + lane;
@@ -1048,7 +1056,8 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
                                              uint64_t* s_rb, int32_t* s_lb, uint16_t* s_ot,
                                              Seg& s_seg, uint32_t& s_si, uint32_t& s_extra,
                                              uint32_t* s_red) {
-  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;
+  // the slim forms only run segments split by column bits (no partitions)
+  constexpr bool kBitsOnly = Lds::slim;
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
   {
@@ -1077,7 +1086,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
                                  : (kPk ? kFieldsPk8 : kFieldsRec);
   const uint32_t* const pk4 = (const uint32_t*)a.rk_out;  // first pass of a packed call
   const uint64_t kbase = sg.cell0 - it->cell_base;  // pass 0: item-local index of the segment
-  const bool track_xfer = pass0 && sg.mode && it->xfer_cells;
+  const bool track_xfer = !kBitsOnly && pass0 && sg.mode && it->xfer_cells;
   // item fields used in the loop, read once
   const int32_t* const i_col = it->col;
   const void* const i_poff = it->poff;
@@ -1090,9 +1099,15 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   const int lg = ow == 8 ? 3 : 2;  // (4-byte offsets keep every payload below 2^31 bytes)
   const uint64_t seg_out = sg.cell0;  // a segment's children share its cell range
 
-  if constexpr (kPass0)
+  if constexpr (kBitsOnly) {
+    if (sg.mode) {  // (the launcher never gives it such a segment)
+      if (threadIdx.x == 0) raise_status(a.item_status, a.abort_flag, it->status_index, MGT_EUNSUPPORTED);
+      return;
+    }
+  } else if constexpr (kPass0) {
     if (sg.mode)
       for (uint32_t i = threadIdx.x; i <= R; i += kBlock) s_lb[i] = (int32_t)gm(it->bounds)[i];
+  }
   // 12-byte packed records (slim records-only pass): each cell's payload
   // offset is stored relative to the first byte of the finish bucket it
   // lands in, digit d's child, kept in s_rb (block-uniform choice)
@@ -1111,7 +1126,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   }
   __syncthreads();
   int osh = 0;
-  if constexpr (kPass0) {
+  if constexpr (kPass0 && !kBitsOnly) {
     if (sg.mode) {  // block-uniform
       osh = owner_shift(s_lb[R]);
       fill_owner_table(s_lb, R, osh, s_ot);
@@ -1119,7 +1134,6 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
     }
   }
   uint64_t src_sub = pass0 ? 0 : a.tsrc[tile];  // level-buffer byte of the sub-chunk (pass >= 2)
-  const uint32_t w = threadIdx.x / kWave, lane = lane_id();
 
   SubLoad cur, nxt;
   {
@@ -1133,6 +1147,11 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
     settle<kFields>(cur, nxt);  // the loop's first iteration then starts from settled registers too
   }
   for (uint64_t c0 = c_begin; c0 < c_end; c0 += kSub) {
+    // the thread index, opaque to the compiler inside each iteration: the
+    // per-cell indexes derived from it are recomputed here instead of being
+    // hoisted out of the loop (and spilled)
+    const uint32_t tid = settled((uint32_t)threadIdx.x);
+    const uint32_t w = tid / kWave, lane = tid % kWave;
     const uint32_t n = (uint32_t)min((uint64_t)kSub, c_end - c0);
     const uint64_t c1 = c0 + kSub;
     uint32_t key[kItems], dg[kItems], sz[kItems], row[kItems], idx[kItems], src[kItems];
@@ -1189,25 +1208,26 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const uint32_t i = w * kWaveCells + r * kWave + lane;
-      dg[r] = i < n ? digit_of(key[r], sg, s_lb, s_ot, osh, R) : 0u;
+      if constexpr (kBitsOnly) dg[r] = i < n ? digit_bits(key[r], sg) : 0u;
+      else dg[r] = i < n ? digit_of(key[r], sg, s_lb, s_ot, osh, R) : 0u;
     }
     // The next sub-chunk's loads go out once this one's registers have been
     // read (the wait counter is in order, so a use of the current loads after
     // issuing these would wait for these too) and fly during the sort.
     if (c1 < c_end) {
       const uint32_t n1 = (uint32_t)min((uint64_t)kSub, c_end - c1);
-      if constexpr (kPk4) load_sub_pk4(nxt, pk4, i_poff, kbase + c1, sg.cell0 + c1, n1, lg, i_fw);
+      if constexpr (kPk4) load_sub_pk4(nxt, pk4, i_poff, kbase + c1, sg.cell0 + c1, n1, lg, i_fw, tid);
       else if constexpr (pass0) load_sub_pass0(nxt, i_col, i_poff, kbase + c1, n1, lg, i_fw,
-                                          kVal ? it->vval : nullptr);
-      else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1);
-      else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1);
+                                          kVal ? it->vval : nullptr, tid);
+      else if constexpr (kPk) load_sub_pk8(nxt, a.ks_in, sg.cell0 + c1, n1, tid);
+      else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1, tid);
     }
-    if constexpr (Lds::slim) {  // packed records-only pass: the whole (column | size) word
-      static_assert(kDefer && kPk, "the slim LDS form is for packed records-only passes");
+    if constexpr (Lds::slim) {  // packed records: the whole (column | size) word
+      static_assert(kPk && (kDefer || kPk4), "the slim LDS form is for packed records");
       uint32_t kw[kItems];
 #pragma unroll
       for (int r = 0; r < kItems; ++r) kw[r] = cur.a[r];
-      sort_sub<false>(L, F, dbits, n, kw, dg, sz, row, idx, src);
+      sort_sub<false>(L, F, dbits, n, kw, dg, sz, row, idx, src, pk_shift);
     } else {
       sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
     }
@@ -1224,10 +1244,10 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       // level buffer, and its byte offset there goes with the record
 #pragma unroll
       for (int r = 0; r < kItems; ++r) {
-        const uint32_t i = r * kBlock + threadIdx.x;
+        const uint32_t i = r * kBlock + tid;
         if (i < n) {
           uint32_t d;
-          if constexpr (Lds::slim) d = digit_of(L.key[i] & pk_mask, sg, s_lb, s_ot, osh, R);
+          if constexpr (Lds::slim) d = digit_bits(L.key[i] & pk_mask, sg);
           else d = L.dig[i];
           const uint64_t cd = seg_out + s_rc[d] + (i - L.wc[d * kNW]);
           const uint64_t so = sub_base + L.src[i];
@@ -1257,40 +1277,51 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
         }
       }
     }
-    // write the sorted cells at their digit's running destination, kPay
-    // cells per lane at a time: payload loads first, then the records, then
-    // the payload stores
+    // write the sorted cells at their digit's running destination, kPayN
+    // cells per lane at a time (two in the slim form, which has fewer
+    // registers): payload loads first, then the records, then the payload
+    // stores
     if constexpr (!kDefer) {
+    constexpr int kPayN = Lds::slim ? 2 : kPay;
 #pragma unroll
-    for (int g = 0; g < kItems; g += kPay) {
-      uint8_t* pd[kPay];
-      const uint8_t* ps[kPay];
-      uint32_t pz[kPay];
-      uint64_t cdst[kPay];
+    for (int g = 0; g < kItems; g += kPayN) {
+      uint8_t* pd[kPayN];
+      const uint8_t* ps[kPayN];
+      uint32_t pz[kPayN];
+      uint64_t cdst[kPayN];
 #pragma unroll
-      for (int q = 0; q < kPay; ++q) {
-        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+      for (int q = 0; q < kPayN; ++q) {
+        const uint32_t i = (g + q) * kBlock + tid;
         pz[q] = 0;
         pd[q] = a.pay_out;
         ps[q] = src_base;
         cdst[q] = 0;
         if (i < n) {
-          const uint32_t d = L.dig[i];
+          uint32_t d;
+          if constexpr (Lds::slim) {  // size and digit from the (column | size) word
+            const uint32_t kw = L.key[i];
+            d = digit_bits(kw & pk_mask, sg);
+            pz[q] = kw >> pk_shift;
+          } else {
+            d = L.dig[i];
+            pz[q] = L.sz[i];
+          }
           const uint32_t ds = L.wc[d * kNW];
           cdst[q] = seg_out + s_rc[d] + (i - ds);
-          pz[q] = L.sz[i];
           pd[q] = a.pay_out + s_rb[d] + (L.bpre[i] - L.bpre[ds]);
           ps[q] = src_base + L.src[i];
         }
       }
-      PayRegs P;
+      PayRegsT<kPayN> P;
       pay_load(P, pd, ps, pz);
 #pragma unroll
-      for (int q = 0; q < kPay; ++q) {
-        const uint32_t i = (g + q) * kBlock + threadIdx.x;
+      for (int q = 0; q < kPayN; ++q) {
+        const uint32_t i = (g + q) * kBlock + tid;
         if (i < n) {
           const uint64_t cd = cdst[q];
-          if constexpr (kPk) {
+          if constexpr (Lds::slim) {
+            a.ks_out[cd] = make_uint2(L.key[i], L.row[i]);  // the whole (column | size) word
+          } else if constexpr (kPk) {
             // a masked column keeps the size intact whatever the input holds
             a.ks_out[cd] = make_uint2((L.key[i] & pk_mask) | (pz[q] << pk_shift), L.row[i]);
           } else {
@@ -1298,7 +1329,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
             a.rk_out[cd] = make_uint2(L.row[i], L.idx[i]);
           }
         }
-        if (xfer_per_cell) {  // the sub-chunk spans source partitions (uniform)
+        if (!kBitsOnly && xfer_per_cell) {  // the sub-chunk spans source partitions (uniform)
           uint32_t key = 0;
           if (i < n) {
             const uint32_t sp = owner_lut(s_lb, s_ot, osh, R, (int64_t)L.row[i]);
@@ -1345,29 +1376,39 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 // on a CU instead of two.
 // kVal (first pass only): every cell carries a value of its own (item vval)
 // in place of its row id, so no rows are expanded.
-// kSlim (the 512-thread records-only pass): packed records only, in the slim
-// LDS form (about 58 KB), two workgroups per CU; it leaves a call whose
-// records could not be packed to the plain kernel launched beside it, which
-// in turn leaves packed calls to it (pk_split).
+// kSlim: packed records only, in the slim LDS form. The 512-thread
+// records-only pass (about 58 KB, two workgroups per CU), or the 256-thread
+// first pass of matrices split by column bits (about 38 KB with the byte
+// prefix, three workgroups per CU instead of two: 161 VGPRs, two payload
+// cells per lane in flight). It leaves a call whose records could not be
+// packed to the plain kernel launched beside it, which in turn leaves packed
+// calls to it (pk_split).
 template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false>
-__global__ __launch_bounds__(kBlock, kSlim ? 2048 / kBlock : (kDefer ? 768 / kBlock : 2))
+__global__ __launch_bounds__(kBlock, kSlim ? (kPass0 ? 768 / kBlock : 2048 / kBlock) : (kDefer ? 768 / kBlock : 2))
 void k_pass_scatter(PassArgs a) {
-  static_assert(!kSlim || (kDefer && !kPass0 && !kVal), "slim: the records-only pass");
-  constexpr int kFan = kPass0 ? kMaxFanout : kFanBits;  // only the first pass may split by partition
+  static_assert(!kSlim || (kPass0 != kDefer && !kVal), "slim: a packed first or records-only pass");
+  // only the first pass may split by partition (not in its slim form)
+  constexpr int kFan = kPass0 ? (kSlim ? 1 << kMaxPassBits : kMaxFanout) : kFanBits;
+  constexpr bool kParts = kPass0 && !kSlim;
   __shared__ SortLdsT<kFan, !kDefer, kSlim> L;
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
   __shared__ uint64_t s_rb[kDefer && !kSlim ? 1 : kFan];  // running destination byte per digit
-                                                          // (slim: each child's first byte)
-  __shared__ int32_t s_lb[kPass0 ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
-  __shared__ uint16_t s_ot[kPass0 ? kOwnerT + 1 : 1];   // their coarse owner table
+                                                          // (slim records-only: each child's first byte)
+  __shared__ int32_t s_lb[kParts ? kMaxParts + 1 : 1];  // partition bounds (partition mode)
+  __shared__ uint16_t s_ot[kParts ? kOwnerT + 1 : 1];   // their coarse owner table
   __shared__ Seg s_seg;
   __shared__ uint32_t s_si, s_extra;
   __shared__ uint32_t s_red[kNW + 1];
   if (aborted(a.abort_flag)) return;
   if constexpr (kSlim) {
-    if (packed_records(a.pk_on, a.no_pack))
-      scatter_body<false, true, false, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
-                                                    s_extra, s_red);
+    if (packed_records(a.pk_on, a.no_pack)) {
+      if constexpr (kPass0)
+        scatter_body<true, false, false, true, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                     s_extra, s_red);
+      else
+        scatter_body<false, true, false, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
+                                                      s_extra, s_red);
+    }
     return;
   } else {
   if constexpr (!kVal && kPass0 != kDefer) {
@@ -2255,7 +2296,14 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
   if (a.g8) {
     if (a.pass == 0 && a.has_val)
       hipLaunchKernelGGL((G::k_pass_scatter<true, false, true>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
-    else if (a.pass == 0)
+    else if (a.pass == 0 && a.pk_on && a.pk_keys && a.slim0) {
+      // packed records in the slim 512-thread form; the plain kernel takes the rest
+      PassArgs b = a;
+      b.pk_split = 1;
+      hipError_t e = launch_pass0_slim(b, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((G::k_pass_scatter<true, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, b);
+    } else if (a.pass == 0)
       hipLaunchKernelGGL((G::k_pass_scatter<true, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
     else if (a.rso_out && a.allow_wide && a.tile_cells >= (uint32_t)kWideSub)
       return launch_pass_scatter_wide(a, s);
@@ -2264,6 +2312,14 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
     else
       hipLaunchKernelGGL((G::k_pass_scatter<false, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+// The caller launches the plain first pass beside it with pk_split set.
+hipError_t launch_pass0_slim(const PassArgs& a, hipStream_t s) {
+  if (a.g8)
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true>), grid1(a.g8), dim3(G::kBlock),
+                       0, s, a);
   return hipGetLastError();
 }
 

@@ -92,8 +92,8 @@ def kernel_bytes(a, stage: str, pass_idx: int, perm: bool, n_passes: int,
 # A reading holds only for the kernel sources it was taken on; after any change
 # to them the traffic figure is reported as null.
 MEASURED_TRAFFIC = {
-    "step": {"sources_sha256": "43f3844400f8a3357b4950963a7db8d7ecf7e4ccf46ec73f8c42ce1c2d1cdd8c",
-             "fetch_kib": 38272712.7, "write_kib": 44259292.2},
+    "step": {"sources_sha256": "1b13ea158b7a145eaeea0683ff29e68c0d7b3d45ff4e9430417c2ffe4449b621",
+             "fetch_kib": 38646225.7, "write_kib": 44311063.0},
 }
 COPY_SCALE = {"fetch": 2.0, "write": 1.0}
 
@@ -102,8 +102,9 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
                          packed: bool = False) -> str:
     """The profiler's name of the kernel behind a stage of one single-matrix
     call (template arguments as the library instantiates them). A packed
-    records-only pass runs in the slim 512-thread kernel (the plain one
-    launched beside it returns at once)."""
+    first pass of a matrix split by column bits (not partitioned) runs in the
+    slim 256-thread kernel, and a packed records-only pass in the slim
+    512-thread kernel (the plain ones launched beside them return at once)."""
     if stage == "hist":
         return "mgt::geo256::k_pass_hist"
     if stage == "finishs":  # the 512-thread whole-bucket finish, two workgroups per CU
@@ -114,7 +115,8 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
         if pass_idx == 0:
-            return "mgt::geo256::k_pass_scatter<true, false, false, false>"
+            return "mgt::geo256::k_pass_scatter<true, false, false, %s>" % (
+                "true" if packed and not partitioned else "false")
         if pass_idx == n_passes - 1:  # records only; 512-thread form for single matrices
             return "mgt::geo512::k_pass_scatter<false, true, false, %s>" % (
                 "true" if packed else "false")

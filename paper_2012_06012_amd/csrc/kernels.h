@@ -49,9 +49,6 @@ struct PassArgs {
   uint32_t tile_cells;        // multiple of kSub
   int32_t offset_width;
   int32_t has_val;            // first pass: the items carry vval (view operations)
-  int32_t allow_wide;         // a single-matrix call: its records-only pass may use the
-                              // kWideBlock / kWideSub geometry (batches keep kBlock: their
-                              // many small segments leave wide workgroups half empty)
   // Packed records: a call with exactly one records-only pass, made without
   // perm and not as a view operation, keeps (column | size << s, row) after
   // the first pass and (column | size << s, row, payload offset) after the

@@ -2305,7 +2305,7 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((G::k_pass_scatter<true, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, b);
     } else if (a.pass == 0)
       hipLaunchKernelGGL((G::k_pass_scatter<true, false, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
-    else if (a.rso_out && a.allow_wide && a.tile_cells >= (uint32_t)kWideSub)
+    else if (a.rso_out && a.tile_cells >= (uint32_t)kWideSub)
       return launch_pass_scatter_wide(a, s);
     else if (a.rso_out)
       hipLaunchKernelGGL((G::k_pass_scatter<false, true, false>), grid1(a.g8), dim3(G::kBlock), 0, s, a);

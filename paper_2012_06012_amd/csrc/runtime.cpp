@@ -98,10 +98,13 @@ int passes_for(int B, int first_cap, int mb, int last_cap) {
 // cells) on small matrices so that about kTargetBuckets workgroups share the
 // finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
 // parallelism. last_cap: the bits the last pass of two or more may take (its
-// 512-thread form takes up to kMaxLastPassBits).
+// 512-thread form takes up to kMaxLastPassBits). level_budget > 0: the passes
+// the call makes anyway (a batch pads every item to its largest pass count),
+// so the finish width is the smallest one from the ideal up that needs no
+// more passes than that, instead of the one that needs the fewest.
 Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
                     const int64_t* bounds, bool partitioned, int mb, int mf, bool spread,
-                    int force_fb, int last_cap) {
+                    int force_fb, int last_cap, int level_budget = 0) {
   Sched s;
   uint64_t width = (uint64_t)std::max<int64_t>(n_cols, 1);
   if (partitioned) {
@@ -128,10 +131,16 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t 
   const int first_cap = partitioned
       ? std::min(mb, R <= (int32_t)part_fan ? floor_log2_u64(part_fan / (uint32_t)R) : 0)
       : mb;
-  // Fewest passes first, then the smallest finish width that achieves them.
+  // Fewest passes first, then the smallest finish width that achieves them
+  // (within a level budget: the smallest finish width that fits it).
   int best_fb = fb_ideal, best_L = 1 << 30;
   for (int fb = fb_ideal; fb <= std::min(mf, K); ++fb) {
     const int L = passes_for(K - fb, first_cap, mb, last_cap);
+    if (level_budget > 0 && L <= level_budget) {
+      best_L = L;
+      best_fb = fb;
+      break;
+    }
     if (L < best_L) { best_L = L; best_fb = fb; }
   }
   if (K <= fb_ideal) { best_fb = K; best_L = 1; }
@@ -166,14 +175,15 @@ constexpr int kWideFinishMinBits = 5;
 // kMaxLastPassBits bits when the pass cap is the full kMaxBitsPerPass.
 // The schedule a setting gives (it may need more than kMaxLevels passes).
 Sched make_sched_tuned(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
-                       const int64_t* bounds, bool partitioned, bool spread, const Tune* t) {
+                       const int64_t* bounds, bool partitioned, bool spread, const Tune* t,
+                       int level_budget = 0) {
   const int mb = (t && t->pass_bits > 0) ? t->pass_bits : max_pass_bits();
   const int ff = (t && t->finish_bits >= 0) ? t->finish_bits : -1;
   const uint32_t tile = (t && t->tile) ? t->tile : tile_cells_for((uint64_t)std::max<int64_t>(nnz, 0));
   const bool wide = spread && tile >= (uint32_t)kWideSub;
   const int last_cap = (wide && mb >= kMaxBitsPerPass) ? kMaxLastPassBits : mb;
   Sched s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, mb, max_finish_bits(),
-                          spread, ff, last_cap);
+                          spread, ff, last_cap, level_budget);
   // A finish bucket of fewer than 2^kWideFinishMinBits columns carries the
   // spread of single column degrees: on skewed inputs many such buckets
   // outgrow the 512-thread finish. The extra last-pass bit is kept only when
@@ -181,13 +191,15 @@ Sched make_sched_tuned(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32
   if (last_cap > mb && s.n_levels >= 2 && s.bits[s.n_levels - 1] > mb &&
       s.finish_bits < kWideFinishMinBits)
     s = make_sched_mb(n_cols, nnz, payload_bytes, R, bounds, partitioned, mb, max_finish_bits(),
-                      spread, ff, mb);
+                      spread, ff, mb, level_budget);
   return s;
 }
 
 Sched make_sched(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t R,
-                 const int64_t* bounds, bool partitioned, bool spread, const Tune* t = nullptr) {
-  Sched s = make_sched_tuned(n_cols, nnz, payload_bytes, R, bounds, partitioned, spread, t);
+                 const int64_t* bounds, bool partitioned, bool spread, const Tune* t = nullptr,
+                 int level_budget = 0) {
+  Sched s = make_sched_tuned(n_cols, nnz, payload_bytes, R, bounds, partitioned, spread, t,
+                             level_budget);
   if (s.n_levels > kMaxLevels) {
     const uint32_t tile = (t && t->tile) ? t->tile : tile_cells_for((uint64_t)std::max<int64_t>(nnz, 0));
     const bool wide = spread && tile >= (uint32_t)kWideSub;
@@ -518,8 +530,8 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
   const int ow = items.empty() ? 8 : items[0].d.offset_width;
   const uint32_t n = y.n_items;
   // Every later pass fits the LDS of the kernel that will run it: 9 bits only
-  // in the last pass of a single-matrix call run in the 512-thread form.
-  const bool wide_last = n == 1 && y.L >= 2 && y.tile_cells >= (uint32_t)kWideSub;
+  // in a last pass run in the 512-thread form (tiles of kWideSub cells or more).
+  const bool wide_last = y.L >= 2 && y.tile_cells >= (uint32_t)kWideSub;
   for (uint32_t i = 0; i < n; ++i)
     for (int l = 1; l < items[i].s.n_levels; ++l) {
       const int cap = (l == y.L - 1 && wide_last) ? kMaxLastPassBits : kMaxPassBits;
@@ -705,7 +717,6 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
     a.tile_cells = y.tile_cells;
     a.offset_width = ow;
     a.has_val = (vc && l == 0) ? 1 : 0;
-    a.allow_wide = n == 1 ? 1 : 0;
     a.pk_on = pk_on;
     a.no_pack = d_no_pack;
     a.pk_keys = pk_keys;
@@ -966,6 +977,21 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
   if (tn > p->lim.max_total_nnz || tc > p->lim.max_total_cols || tr > p->lim.max_total_rows ||
       tp > p->lim.max_total_parts)
     return MGT_EUNSUPPORTED;
+  // Every item makes as many passes as the item that needs the most (the
+  // layout pads the others with 0-bit passes, which copy their records). An
+  // item whose fewest passes come from a wider finish than its ideal takes
+  // the padded passes' bits instead, keeping finish buckets near 2 * kSub
+  // cells (wider ones outgrow the whole-bucket finish).
+  int L = 1;
+  for (const HostItem& it : items) L = std::max(L, it.s.n_levels);
+  for (int32_t i = 0; i < n && L > 1; ++i) {
+    HostItem& it = items[(size_t)i];
+    if (it.s.n_levels >= L) continue;
+    const mgt_desc& d = in[i].desc;
+    const Sched s = make_sched(d.n_cols, d.nnz, d.payload_bytes, d.n_parts, d.part_bounds,
+                               d.n_parts > 1, false, &tune, L);
+    if (s.n_levels <= L) it.s = s;
+  }
   return MGT_OK;
 }
 

@@ -120,6 +120,27 @@ def test_batch_packed_records(wide_cell, monkeypatch):
                 assert np.array_equal(v, h2[k]), k
 
 
+def test_batch_items_take_the_padded_passes():
+    # every item of a batch makes as many passes as the item that needs the
+    # most; an item whose fewest passes would come from wide finish buckets
+    # (100,000 columns of ~60 cells: one pass and 512-column buckets of about
+    # 30,000 cells) takes the second pass's bits instead and keeps buckets
+    # near 4,096 cells; packed 12-byte records through the 512-thread pass
+    from paper_2012_06012_amd import mgt
+    items = [gen.random_small(31, n_rows=1 << 19, n_cols=1 << 19, deg_mean=8.0, w_lo=0, w_hi=13),
+             gen.random_small(32, n_rows=100000, n_cols=100000, deg_mean=60.0, w_lo=0, w_hi=9),
+             gen.random_small(33, n_rows=3000, n_cols=3000, deg_mean=5.0, w_lo=0, w_hi=20)]
+    outs, st = _run_batch(items, perm=False)
+    assert (st == 0).all()
+    for a, h in zip(items, outs):
+        assert_matches_oracle(a, h)
+        o, s1 = mgt.transpose(to_device(a), perm=False)
+        hs = host(o)
+        for k, v in hs.items():
+            if v is not None:
+                assert np.array_equal(v, h[k]), k
+
+
 def test_batch_packed_with_fixed_width_items():
     # fixed-width items beside variable ones in one packed two-pass batch: the
     # first pass then reads columns and offsets (or k * width) for every item

@@ -1,7 +1,7 @@
 """GPU parity of the packed record form.
 
-A single-matrix call whose schedule has one records-only pass, made without
-a permutation output, carries each cell as (column | size << column bits,
+A call whose schedule has one records-only pass, made without a permutation
+output, carries each cell as (column | size << column bits,
 row) after the first pass and (column | size << column bits, row, payload
 offset) after the second, instead of separate (column, size), (row, cell
 index) and offset records. The first histogram checks that every payload

@@ -95,6 +95,6 @@ def test_batch_mixed_schedule_lengths(monkeypatch):
 @pytest.mark.parametrize("caps", [(8, 7), (5, 5)])  # 2 and 3 passes
 def test_wide_records_pass(monkeypatch, caps):
     # 8 M cells: 8,192-cell tiles, so the records-only last pass runs with
-    # 512-thread workgroups and 4,096-cell sub-chunks (single-matrix calls)
+    # 512-thread workgroups and 4,096-cell sub-chunks
     _caps(monkeypatch, *caps)
     _both(gen.large(seed=5, scale=6))

@@ -781,7 +781,14 @@ __device__ __forceinline__ uint32_t expand_rows(const void* rp, int ow, uint64_t
 // are loaded into registers up front (`fast`) as at most three pieces per
 // cell (16, 16 or 8 + 4 bytes; dword-aligned multi-dword accesses are legal
 // on gfx950), so a wave moves a cell in up to three instructions instead of
-// up to eight; otherwise the cells are copied one by one in the store phase.
+// up to eight. When every cell is at most 16 bytes at any alignment
+// (`small`), the loads take the one or two 16-byte-aligned blocks that hold
+// its bytes (an aligned block lies within one page, so reading all of it is
+// safe), and the stores write exactly the cell's bytes: bytes up to the first
+// dword boundary of the destination, the dwords after it (the source bytes
+// shifted into place in registers), then the remaining bytes. Otherwise the
+// cells are copied one by one in the store phase (up to 32 bytes the same
+// way, in two halves).
 constexpr int kPay = 4;  // cells per lane whose payload words are held at once
 
 typedef uint32_t u32x4a __attribute__((ext_vector_type(4), aligned(4)));
@@ -795,20 +802,103 @@ static_assert(sizeof(Rec12) == 12, "12-byte record");
 template <int N>
 struct PayRegsT {
   u32x4a v[N][2];
-  bool fast;
+  bool fast, small;
 };
+
+// The 4 bytes at byte b (0..3) of the 8-byte value hi:lo.
+__device__ __forceinline__ uint32_t funnel_bytes(uint32_t hi, uint32_t lo, uint32_t b) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8u * b));
+}
+// w[q + j] for q in 0..4, without indexing registers by a lane value.
+__device__ __forceinline__ uint32_t pick5(uint32_t q, const uint32_t* w, int j) {
+  return q == 0 ? w[j] : q == 1 ? w[j + 1] : q == 2 ? w[j + 2] : q == 3 ? w[j + 3] : w[j + 4];
+}
+
+// Stores the n <= 16 bytes that start at byte o (0..15) of the 32-byte window
+// v (the source's aligned blocks) to dst, touching no byte outside
+// [dst, dst + n).
+__device__ __forceinline__ void store_small(uint8_t* dst, const u32x4a (&v)[2], uint32_t o,
+                                            uint32_t n) {
+  const uint32_t w[10] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w, 0u, 0u};
+  GMEM uint8_t* const d = gm(dst);
+  const uint32_t hd = min((4u - ((uint32_t)(uintptr_t)dst & 3u)) & 3u, n);  // bytes before a dword boundary
+  const uint32_t qh = o >> 2;
+  const uint32_t hv = funnel_bytes(pick5(qh, w, 1), pick5(qh, w, 0), o & 3u);
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if ((uint32_t)j < hd) d[j] = (uint8_t)(hv >> (8 * j));
+  const uint32_t x = o + hd, q = x >> 2, b = x & 3u;  // the dwords after the head
+  uint32_t t[6], mid[5];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) t[j] = pick5(q, w, j);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) mid[k] = funnel_bytes(t[k + 1], t[k], b);
+  const uint32_t nm = (n - hd) >> 2, nt = (n - hd) & 3u;
+  GMEM uint32_t* const da = (GMEM uint32_t*)(d + hd);
+  if (nm == 4u) {
+    *(GMEM u32x4a*)da = u32x4a{mid[0], mid[1], mid[2], mid[3]};
+  } else {
+    if (nm & 2u) *(GMEM u32x2a*)da = u32x2a{mid[0], mid[1]};
+    if (nm & 1u) da[nm & 2u] = (nm & 2u) ? mid[2] : mid[0];
+  }
+  const uint32_t tv = nm == 0 ? mid[0] : nm == 1 ? mid[1] : nm == 2 ? mid[2] : nm == 3 ? mid[3] : mid[4];
+  GMEM uint8_t* const dt = (GMEM uint8_t*)(da + nm);
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+    if ((uint32_t)j < nt) dt[j] = (uint8_t)(tv >> (8 * j));
+}
 using PayRegs = PayRegsT<kPay>;
+
+// Copies n <= 32 bytes of any alignment the same way, in two halves: the
+// 16-byte-aligned blocks that hold the cell (up to three) are loaded first.
+__device__ __forceinline__ void copy_medium(uint8_t* dst, const uint8_t* src, uint32_t n) {
+  const uint32_t o = (uint32_t)(uintptr_t)src & 15u;
+  const GMEM v4u* const b = (const GMEM v4u*)gm(src - o);  // 16-byte aligned
+  u32x4a v[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    v[k] = u32x4a{0u, 0u, 0u, 0u};
+    if (o + n > 16u * (uint32_t)k) {  // block k holds a byte of the cell
+      const v4u x = b[k];
+      v[k] = u32x4a{x.x, x.y, x.z, x.w};
+    }
+  }
+  const u32x4a lo[2] = {v[0], v[1]}, hi[2] = {v[1], v[2]};
+  store_small(dst, lo, o, n < 16u ? n : 16u);
+  if (n > 16u) store_small(dst + 16, hi, o, n - 16u);
+}
 
 template <int N>
 __device__ __forceinline__ void pay_load(PayRegsT<N>& P, uint8_t* const (&dst)[N],
                                          const uint8_t* const (&src)[N],
                                          const uint32_t (&sz)[N]) {
-  bool fast = true;
+  bool fast = true, small = true;
 #pragma unroll
-  for (int r = 0; r < N; ++r)
+  for (int r = 0; r < N; ++r) {
     fast &= sz[r] == 0u ||
             (sz[r] <= 32u && ((sz[r] | (uint32_t)(uintptr_t)src[r] | (uint32_t)(uintptr_t)dst[r]) & 3u) == 0);
+    small &= sz[r] <= 16u;
+  }
   P.fast = fast;
+  P.small = !fast && small;
+  if (P.small) {
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      const uint32_t z = sz[r];
+      const uint32_t o = (uint32_t)(uintptr_t)src[r] & 15u;
+      const GMEM v4u* const b = (const GMEM v4u*)gm(src[r] - o);  // 16-byte aligned
+      P.v[r][0] = u32x4a{0u, 0u, 0u, 0u};
+      P.v[r][1] = u32x4a{0u, 0u, 0u, 0u};
+      if (z) {
+        const v4u x = b[0];
+        P.v[r][0] = u32x4a{x.x, x.y, x.z, x.w};
+      }
+      if (o + z > 16u) {
+        const v4u y = b[1];
+        P.v[r][1] = u32x4a{y.x, y.y, y.z, y.w};
+      }
+    }
+  }
   if (fast) {
 #pragma unroll
     for (int r = 0; r < N; ++r) {
@@ -844,25 +934,16 @@ __device__ __forceinline__ void pay_store(const PayRegsT<N>& P, uint8_t* const (
         if (rem & 4u) *(GMEM uint32_t*)(d + o1 + (rem & 8u)) = P.v[r][1].z;
       }
     }
+  } else if (P.small) {
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+      if (sz[r]) store_small(dst[r], P.v[r], (uint32_t)(uintptr_t)src[r] & 15u, sz[r]);
   } else {
-    bool small = true;
 #pragma unroll
-    for (int r = 0; r < N; ++r) small &= sz[r] <= 16u;
-    if (small) {
-      uint8_t v[N][16];
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[r]) v[r][j] = gm(src[r])[j];
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if ((uint32_t)j < sz[r]) gm(dst[r])[j] = v[r][j];
-    } else {
-      for (int r = 0; r < N; ++r)
-        if (sz[r]) copy_cell(dst[r], src[r], sz[r]);
+    for (int r = 0; r < N; ++r) {
+      if (sz[r] == 0u) continue;
+      if (sz[r] <= 32u) copy_medium(dst[r], src[r], sz[r]);
+      else copy_cell(dst[r], src[r], sz[r]);
     }
   }
 }

@@ -275,3 +275,41 @@ def test_twelve_byte_records_all_finish_forms(threads, monkeypatch):
     from paper_2012_06012_amd import mgt
     assert mgt.plan_for(to_device(a), 0).schedule()["tile_cells"] >= 4096
     _check(a, False, 0, monkeypatch)
+
+
+@pytest.mark.parametrize("form", ["packed", "wide", "perm", "partitioned"])
+def test_unaligned_cells_every_offset(form, monkeypatch):
+    # cell sizes 0..40 bytes in a cycle, so source offsets take every value
+    # modulo 16 and destination offsets every value modulo 4: cells of up to
+    # 16 bytes (one or two aligned source blocks held in registers), 17 to 32
+    # (copied in two halves) and longer (copied piece by piece), through the
+    # first pass, the records-only pass and every finish form
+    from paper_2012_06012_amd import mgt
+    rng = np.random.default_rng(91)
+    n_rows, n_cols = 30000, 1 << 14
+    deg = rng.poisson(12.0, size=n_rows)
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
+    for i in range(n_rows):
+        col[rp[i]:rp[i + 1]].sort()
+    widths = (np.arange(nnz) * 7 + rng.integers(0, 3, size=nnz)) % 41
+    parts = 8 if form == "partitioned" else 1
+    bounds = None
+    if parts > 1:
+        bounds = np.linspace(0, n_rows, parts + 1).astype(np.int64)
+        n_cols = n_rows  # partitioned matrices are square
+        col = (col.astype(np.int64) * n_rows // (1 << 14)).astype(np.int32)
+        for i in range(n_rows):
+            col[rp[i]:rp[i + 1]].sort()
+    a = from_arrays(n_rows, n_cols, rp, col, widths=widths, fill_seed=92, bounds=bounds)
+    if form == "wide":
+        monkeypatch.setenv("MGT_NO_PACK", "1")
+    d = to_device(a)
+    for tile in (0, 4096):
+        plan = mgt.plan_for(d, mgt.EMIT_PERM if form == "perm" else 0)
+        plan.set_schedule(8, -1, tile)
+        out, st = mgt.transpose(d, plan=plan, perm=form == "perm", partitioned=parts > 1)
+        assert int(st.cpu()[0]) == 0
+        assert_matches_oracle(a, host(out), partitioned=parts > 1)

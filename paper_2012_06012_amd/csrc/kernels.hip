@@ -809,9 +809,29 @@ struct PayRegsT {
 __device__ __forceinline__ uint32_t funnel_bytes(uint32_t hi, uint32_t lo, uint32_t b) {
   return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8u * b));
 }
-// w[q + j] for q in 0..4, without indexing registers by a lane value.
-__device__ __forceinline__ uint32_t pick5(uint32_t q, const uint32_t* w, int j) {
-  return q == 0 ? w[j] : q == 1 ? w[j + 1] : q == 2 ? w[j + 2] : q == 3 ? w[j + 3] : w[j + 4];
+// a_q for q in 0..4, without indexing registers by a lane value: a
+// multiplexer on the bits of q, on values (a chain of equality tests, or
+// selects between elements of one array, end up as loads from scratch memory).
+__device__ __forceinline__ uint32_t mux5(uint32_t q, uint32_t a0, uint32_t a1, uint32_t a2,
+                                         uint32_t a3, uint32_t a4) {
+  const uint32_t a = (q & 1u) ? a1 : a0;
+  const uint32_t b = (q & 1u) ? a3 : a2;
+  const uint32_t c = (q & 2u) ? b : a;
+  return (q & 4u) ? a4 : c;
+}
+// The dwords 0..5 of the window w0..w8 (w9 = 0) shifted down by q (0..4)
+// dwords, then the five dwords starting b (0..3) bytes into that.
+struct Shifted5 {
+  uint32_t m0, m1, m2, m3, m4;
+};
+__device__ __forceinline__ Shifted5 shift_window(uint32_t q, uint32_t b, uint32_t w0, uint32_t w1,
+                                                 uint32_t w2, uint32_t w3, uint32_t w4, uint32_t w5,
+                                                 uint32_t w6, uint32_t w7, uint32_t w8) {
+  const uint32_t t0 = mux5(q, w0, w1, w2, w3, w4), t1 = mux5(q, w1, w2, w3, w4, w5);
+  const uint32_t t2 = mux5(q, w2, w3, w4, w5, w6), t3 = mux5(q, w3, w4, w5, w6, w7);
+  const uint32_t t4 = mux5(q, w4, w5, w6, w7, w8), t5 = mux5(q, w5, w6, w7, w8, 0u);
+  return Shifted5{funnel_bytes(t1, t0, b), funnel_bytes(t2, t1, b), funnel_bytes(t3, t2, b),
+                  funnel_bytes(t4, t3, b), funnel_bytes(t5, t4, b)};
 }
 
 // Stores the n <= 16 bytes that start at byte o (0..15) of the 32-byte window
@@ -819,29 +839,26 @@ __device__ __forceinline__ uint32_t pick5(uint32_t q, const uint32_t* w, int j) 
 // [dst, dst + n).
 __device__ __forceinline__ void store_small(uint8_t* dst, const u32x4a (&v)[2], uint32_t o,
                                             uint32_t n) {
-  const uint32_t w[10] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w, 0u, 0u};
+  const uint32_t w0 = v[0].x, w1 = v[0].y, w2 = v[0].z, w3 = v[0].w;
+  const uint32_t w4 = v[1].x, w5 = v[1].y, w6 = v[1].z, w7 = v[1].w;
   GMEM uint8_t* const d = gm(dst);
   const uint32_t hd = min((4u - ((uint32_t)(uintptr_t)dst & 3u)) & 3u, n);  // bytes before a dword boundary
   const uint32_t qh = o >> 2;
-  const uint32_t hv = funnel_bytes(pick5(qh, w, 1), pick5(qh, w, 0), o & 3u);
+  const uint32_t hv = funnel_bytes(mux5(qh, w1, w2, w3, w4, w5), mux5(qh, w0, w1, w2, w3, w4), o & 3u);
 #pragma unroll
   for (int j = 0; j < 3; ++j)
     if ((uint32_t)j < hd) d[j] = (uint8_t)(hv >> (8 * j));
-  const uint32_t x = o + hd, q = x >> 2, b = x & 3u;  // the dwords after the head
-  uint32_t t[6], mid[5];
-#pragma unroll
-  for (int j = 0; j < 6; ++j) t[j] = pick5(q, w, j);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) mid[k] = funnel_bytes(t[k + 1], t[k], b);
+  const uint32_t x = o + hd;  // the dwords after the head
+  const Shifted5 m = shift_window(x >> 2, x & 3u, w0, w1, w2, w3, w4, w5, w6, w7, 0u);
   const uint32_t nm = (n - hd) >> 2, nt = (n - hd) & 3u;
   GMEM uint32_t* const da = (GMEM uint32_t*)(d + hd);
   if (nm == 4u) {
-    *(GMEM u32x4a*)da = u32x4a{mid[0], mid[1], mid[2], mid[3]};
+    *(GMEM u32x4a*)da = u32x4a{m.m0, m.m1, m.m2, m.m3};
   } else {
-    if (nm & 2u) *(GMEM u32x2a*)da = u32x2a{mid[0], mid[1]};
-    if (nm & 1u) da[nm & 2u] = (nm & 2u) ? mid[2] : mid[0];
+    if (nm & 2u) *(GMEM u32x2a*)da = u32x2a{m.m0, m.m1};
+    if (nm & 1u) da[nm & 2u] = (nm & 2u) ? m.m2 : m.m0;
   }
-  const uint32_t tv = nm == 0 ? mid[0] : nm == 1 ? mid[1] : nm == 2 ? mid[2] : nm == 3 ? mid[3] : mid[4];
+  const uint32_t tv = mux5(nm, m.m0, m.m1, m.m2, m.m3, m.m4);
   GMEM uint8_t* const dt = (GMEM uint8_t*)(da + nm);
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -2168,21 +2185,45 @@ __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
         // cell in whole 16-byte pieces (reading up to 12 bytes past it, inside
         // the level buffer's padding), the wave packs its 64 cells' bytes in
         // LDS in output order, and writes them back as 16 contiguous bytes
-        // per lane. Other payloads are copied lane by lane.
+        // per lane. Payloads of up to 16 bytes at any alignment (`ustaged`)
+        // pass through LDS too: each lane loads the 16-byte-aligned blocks
+        // that hold its cell, shifts its bytes to their place in the wave's
+        // run and ORs them into the zeroed stage, and the run is written back
+        // 16 bytes per lane, with dword and byte stores at its two ends.
+        // Other payloads are copied lane by lane.
         PayRegsT<kBkPay> P;
-        bool staged = true;
+        bool staged = true, small = true;
 #pragma unroll
-        for (int q = 0; q < kBkPay; ++q)
+        for (int q = 0; q < kBkPay; ++q) {
           staged &= pz[q] == 0u ||
                     (pz[q] <= 32u &&
                      ((pz[q] | (uint32_t)(uintptr_t)ps[q] | (uint32_t)(uintptr_t)pd[q]) & 3u) == 0);
+          small &= pz[q] <= 16u;
+        }
         staged = __all(staged);
+        const bool ustaged = !staged && __all(small);
         if (staged) {
 #pragma unroll
           for (int q = 0; q < kBkPay; ++q) {
             const GMEM uint8_t* sp = gm(ps[q]);
             if (pz[q]) P.v[q][0] = *(const GMEM u32x4a*)sp;
             if (pz[q] > 16u) P.v[q][1] = *(const GMEM u32x4a*)(sp + 16);
+          }
+        } else if (ustaged) {
+#pragma unroll
+          for (int q = 0; q < kBkPay; ++q) {
+            const uint32_t o = (uint32_t)(uintptr_t)ps[q] & 15u;
+            const GMEM v4u* const bk = (const GMEM v4u*)gm(ps[q] - o);  // 16-byte aligned
+            P.v[q][0] = u32x4a{0u, 0u, 0u, 0u};
+            P.v[q][1] = u32x4a{0u, 0u, 0u, 0u};
+            if (pz[q]) {
+              const v4u x = bk[0];
+              P.v[q][0] = u32x4a{x.x, x.y, x.z, x.w};
+            }
+            if (o + pz[q] > 16u) {
+              const v4u y = bk[1];
+              P.v[q][1] = u32x4a{y.x, y.y, y.z, y.w};
+            }
           }
         } else {
           pay_load(P, pd, ps, pz);
@@ -2222,6 +2263,67 @@ __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
                 *(GMEM u32x4a*)(dst + o) = u32x4a{sw[0], sw[1], sw[2], sw[3]};
               } else {
                 for (uint32_t j = 0; j < ((tot - o) >> 2); ++j) ((GMEM uint32_t*)(dst + o))[j] = sw[j];
+              }
+            }
+          }
+        } else if (ustaged) {
+          // stage dword 0 holds the dword-aligned address below the run's
+          // first byte; a run of 64 cells of up to 16 bytes spans at most 257
+          // of the wave's 512 stage dwords
+          uint32_t* const stage = (uint32_t*)L.wc + w * (kWave * 8);
+#pragma unroll
+          for (int q = 0; q < kBkPay; ++q) {
+            const uint32_t p = (uint32_t)(g + q) * kBkBlock + tid;
+            const uint64_t act = ballot(p < len);  // a prefix of the wave's lanes
+            if (act == 0) continue;                // wave-uniform
+            const uint32_t last = 63u - (uint32_t)__clzll(act);
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)pb[q]);
+            const uint32_t rel = pb[q] - b0;
+            const uint32_t tot =
+                (uint32_t)__builtin_amdgcn_readlane((int)(rel + pz[q]), (int)last);
+            uint8_t* const run = o_pay + out_byte0 + b0;
+            const uint32_t sh = (uint32_t)(uintptr_t)run & 3u;
+            const uint32_t end = sh + tot;  // stage bytes [sh, end) are the run's
+            for (uint32_t e = lane; e < ((end + 3u) >> 2); e += kWave) stage[e] = 0u;
+            const uint32_t z = pz[q];
+            if (z) {
+              const uint32_t sb = sh + rel, r = sb & 3u, d0 = sb >> 2;
+              // the window with a zero dword in front, so the shift is >= 0
+              const uint32_t x = ((uint32_t)(uintptr_t)ps[q] & 15u) + 4u - r;  // 1..19
+              const Shifted5 m = shift_window(x >> 2, x & 3u, 0u, P.v[q][0].x, P.v[q][0].y,
+                                              P.v[q][0].z, P.v[q][0].w, P.v[q][1].x, P.v[q][1].y,
+                                              P.v[q][1].z, P.v[q][1].w);
+              const uint32_t mv[5] = {m.m0, m.m1, m.m2, m.m3, m.m4};
+              const uint32_t nd = (r + z + 3u) >> 2;
+#pragma unroll
+              for (int k = 0; k < 5; ++k) {
+                if ((uint32_t)k < nd) {
+                  const int lo = min(max((int)r - 4 * k, 0), 4);
+                  const int hi = min(max((int)(r + z) - 4 * k, 0), 4);
+                  const uint32_t mk = (hi >= 4 ? ~0u : (1u << (8 * hi)) - 1u) & ~((1u << (8 * lo)) - 1u);
+                  __hip_atomic_fetch_or(&stage[d0 + k], mv[k] & mk, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+              }
+            }
+            GMEM uint8_t* const base = gm(run - sh);  // dword aligned
+            for (uint32_t o = lane * 16u; o < end; o += kWave * 16u) {
+              const uint32_t* sw = stage + (o >> 2);
+              if (o >= sh && o + 16u <= end) {
+                *(GMEM u32x4a*)(base + o) = u32x4a{sw[0], sw[1], sw[2], sw[3]};
+              } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const uint32_t a0 = o + 4u * (uint32_t)j;
+                  if (a0 >= sh && a0 + 4u <= end) {
+                    *(GMEM uint32_t*)(base + a0) = sw[j];
+                  } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                      if (a0 + (uint32_t)i >= sh && a0 + (uint32_t)i < end)
+                        base[a0 + (uint32_t)i] = (uint8_t)(sw[j] >> (8 * i));
+                  }
+                }
               }
             }
           }

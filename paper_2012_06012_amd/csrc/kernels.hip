@@ -2159,7 +2159,9 @@ __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
       int32_t* const o_col = it->t_col;
       void* const o_poff = it->t_poff;
       const uint8_t* const src_base = a.pay_in + blo;
-#pragma unroll
+      // (kept rolled: with its three copy paths the body is too large to
+      // unroll five times)
+#pragma unroll 1
       for (int g = 0; g < kBkItems; g += kBkPay) {
         uint8_t* pd[kBkPay];
         const uint8_t* ps[kBkPay];

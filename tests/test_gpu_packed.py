@@ -313,3 +313,31 @@ def test_unaligned_cells_every_offset(form, monkeypatch):
         out, st = mgt.transpose(d, plan=plan, perm=form == "perm", partitioned=parts > 1)
         assert int(st.cpu()[0]) == 0
         assert_matches_oracle(a, host(out), partitioned=parts > 1)
+
+
+@pytest.mark.parametrize("threads", [None, "512", "1024"])
+def test_unaligned_small_cells_staged_finish(threads, monkeypatch):
+    # every cell of 0 to 16 bytes at any alignment: whole rounds of the
+    # bucket finish take the staged path for unaligned cells (bytes shifted
+    # into the wave's run in LDS), the first pass the register copy
+    if threads is not None:
+        monkeypatch.setenv("MGT_BUCKET_THREADS", threads)
+    rng = np.random.default_rng(93)
+    n_rows, n_cols = 60000, 1 << 15
+    deg = rng.poisson(16.0, size=n_rows)
+    rp = np.zeros(n_rows + 1, dtype=np.int64)
+    np.cumsum(deg, out=rp[1:])
+    nnz = int(rp[-1])
+    col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
+    for i in range(n_rows):
+        col[rp[i]:rp[i + 1]].sort()
+    widths = rng.integers(0, 17, size=nnz)
+    a = from_arrays(n_rows, n_cols, rp, col, widths=widths, fill_seed=94)
+    from paper_2012_06012_amd import mgt
+    d = to_device(a)
+    for tile in (0, 4096):
+        plan = mgt.plan_for(d, 0)
+        plan.set_schedule(8, -1, tile)
+        out, st = mgt.transpose(d, plan=plan)
+        assert int(st.cpu()[0]) == 0
+        assert_matches_oracle(a, host(out))

@@ -96,8 +96,8 @@ int passes_for(int B, int first_cap, int mb, int last_cap) {
 
 // spread: a single-matrix call, whose finish buckets shrink (down to kSub / 8
 // cells) on small matrices so that about kTargetBuckets workgroups share the
-// finish; a batch keeps ~2 * kSub cells per bucket, its items giving the
-// parallelism. last_cap: the bits the last pass of two or more may take (its
+// finish; a batch keeps 2 to 4 * kSub cells per bucket (the 1,024-thread
+// whole-bucket finish holds up to 9,216), its items giving the parallelism. last_cap: the bits the last pass of two or more may take (its
 // 512-thread form takes up to kMaxLastPassBits). level_budget > 0: the passes
 // the call makes anyway (a batch pads every item to its largest pass count),
 // so the finish width is the smallest one from the ideal up that needs no
@@ -114,11 +114,12 @@ Sched make_sched_mb(int64_t n_cols, int64_t nnz, int64_t payload_bytes, int32_t 
   }
   const int K = ceil_log2_u64(width);
   s.key_bits = K;
-  // Finish buckets of ~2 * kSub cells: 2^fb columns at nnz / n_cols cells each.
+  // Finish buckets of up to 2 * kSub cells (a batch: 4 * kSub): 2^fb columns
+  // at nnz / n_cols cells each.
   int fb_ideal = 0;
   if (nnz > 0 && n_cols > 0) {
     const double per_col = (double)nnz / (double)n_cols;
-    double target = 2.0 * kSub;
+    double target = (spread ? 2.0 : 4.0) * kSub;
     if (spread)
       target = std::min(target, std::max(kSub / 8.0, (double)nnz / (double)kTargetBuckets));
     fb_ideal = floor_log2_u64((uint64_t)std::max(1.0, target / per_col));
@@ -980,7 +981,7 @@ int batch_items(mgt_plan_s* p, const mgt_item* in, int32_t n, std::vector<HostIt
   // Every item makes as many passes as the item that needs the most (the
   // layout pads the others with 0-bit passes, which copy their records). An
   // item whose fewest passes come from a wider finish than its ideal takes
-  // the padded passes' bits instead, keeping finish buckets near 2 * kSub
+  // the padded passes' bits instead, keeping finish buckets near 4 * kSub
   // cells (wider ones outgrow the whole-bucket finish).
   int L = 1;
   for (const HostItem& it : items) L = std::max(L, it.s.n_levels);

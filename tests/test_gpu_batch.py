@@ -125,7 +125,7 @@ def test_batch_items_take_the_padded_passes():
     # most; an item whose fewest passes would come from wide finish buckets
     # (100,000 columns of ~60 cells: one pass and 512-column buckets of about
     # 30,000 cells) takes the second pass's bits instead and keeps buckets
-    # near 4,096 cells; packed 12-byte records through the 512-thread pass
+    # of up to 8,192 cells; packed 12-byte records through the 512-thread pass
     from paper_2012_06012_amd import mgt
     items = [gen.random_small(31, n_rows=1 << 19, n_cols=1 << 19, deg_mean=8.0, w_lo=0, w_hi=13),
              gen.random_small(32, n_rows=100000, n_cols=100000, deg_mean=60.0, w_lo=0, w_hi=9),

@@ -315,8 +315,9 @@ def test_unaligned_cells_every_offset(form, monkeypatch):
         assert_matches_oracle(a, host(out), partitioned=parts > 1)
 
 
+@pytest.mark.parametrize("ow", [8, 4])
 @pytest.mark.parametrize("threads", [None, "512", "1024"])
-def test_unaligned_small_cells_staged_finish(threads, monkeypatch):
+def test_unaligned_small_cells_staged_finish(threads, ow, monkeypatch):
     # every cell of 0 to 16 bytes at any alignment: whole rounds of the
     # bucket finish take the staged path for unaligned cells (bytes shifted
     # into the wave's run in LDS), the first pass the register copy
@@ -332,7 +333,7 @@ def test_unaligned_small_cells_staged_finish(threads, monkeypatch):
     for i in range(n_rows):
         col[rp[i]:rp[i + 1]].sort()
     widths = rng.integers(0, 17, size=nnz)
-    a = from_arrays(n_rows, n_cols, rp, col, widths=widths, fill_seed=94)
+    a = from_arrays(n_rows, n_cols, rp, col, widths=widths, offset_width=ow, fill_seed=94)
     from paper_2012_06012_amd import mgt
     d = to_device(a)
     for tile in (0, 4096):

@@ -102,9 +102,9 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
                          packed: bool = False) -> str:
     """The profiler's name of the kernel behind a stage of one single-matrix
     call (template arguments as the library instantiates them). A packed
-    first pass of a matrix split by column bits (not partitioned) runs in the
-    slim 256-thread kernel, and a packed records-only pass in the slim
-    512-thread kernel (the plain ones launched beside them return at once)."""
+    first pass runs in the slim 256-thread kernel (its partition form when
+    partitioned), and a packed records-only pass in the slim 512-thread
+    kernel (the plain ones launched beside them return at once)."""
     if stage == "hist":
         return "mgt::geo256::k_pass_hist"
     if stage == "finishs":  # the 512-thread whole-bucket finish, two workgroups per CU
@@ -115,12 +115,14 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
         if pass_idx == 0:
-            return "mgt::geo256::k_pass_scatter<true, false, false, %s>" % (
-                "true" if packed and not partitioned else "false")
+            if packed:
+                return "mgt::geo256::k_pass_scatter<true, false, false, true, %s>" % (
+                    "true" if partitioned else "false")
+            return "mgt::geo256::k_pass_scatter<true, false, false, false, false>"
         if pass_idx == n_passes - 1:  # records only; 512-thread form for single matrices
-            return "mgt::geo512::k_pass_scatter<false, true, false, %s>" % (
+            return "mgt::geo512::k_pass_scatter<false, true, false, %s, false>" % (
                 "true" if packed else "false")
-        return "mgt::geo256::k_pass_scatter<false, false, false, false>"
+        return "mgt::geo256::k_pass_scatter<false, false, false, false, false>"
     return stage
 
 

@@ -62,8 +62,10 @@ struct PassArgs {
                               // reads instead of the columns and offsets
   int32_t pk_split;           // set by the launcher: a slim packed-only kernel runs beside this
                               // one and takes packed records (this one returns on them)
-  int32_t slim0;              // first pass of a call whose items are all split by column bits
-                              // (no partitions): packed records go to the slim first pass
+  int32_t slim0;              // first pass: packed records go to the slim first pass, in its
+                              // bits-only form (1: every item split by column bits) or its
+                              // partition form (2: some item split by partition, fan-out
+                              // at most 512); 0: the plain kernel only
   int32_t rec12;              // the slim kernel writes 12-byte packed records (column | size,
                               // row, payload offset minus the finish bucket's first byte as a
                               // signed 32-bit word) unless *big_seg is set

@@ -1149,13 +1149,14 @@ __device__ __forceinline__ void sizes_from_offsets(const SubLoad& S, uint32_t (&
 
 // kPk: packed records (see load_sub_pk8); only the first pass of a plain
 // (not view) call and the records-only pass have a packed form.
-template <bool kPass0, bool kDefer, bool kVal, bool kPk, bool kKeys, class Lds>
+template <bool kPass0, bool kDefer, bool kVal, bool kPk, bool kKeys, class Lds, bool kSlimParts = false>
 __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t* s_rc,
                                              uint64_t* s_rb, int32_t* s_lb, uint16_t* s_ot,
                                              Seg& s_seg, uint32_t& s_si, uint32_t& s_extra,
                                              uint32_t* s_red) {
-  // the slim forms only run segments split by column bits (no partitions)
-  constexpr bool kBitsOnly = Lds::slim;
+  // the slim forms run only segments split by column bits, except the slim
+  // first pass built for partitions (kSlimParts)
+  constexpr bool kBitsOnly = Lds::slim && !kSlimParts;
   const uint64_t tile = xcd_tile(blockIdx.x, a.g8);
   if (tile >= a.tstart[a.nseg]) return;
   {
@@ -1398,7 +1399,8 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
           uint32_t d;
           if constexpr (Lds::slim) {  // size and digit from the (column | size) word
             const uint32_t kw = L.key[i];
-            d = digit_bits(kw & pk_mask, sg);
+            if constexpr (kBitsOnly) d = digit_bits(kw & pk_mask, sg);
+            else d = digit_of(kw & pk_mask, sg, s_lb, s_ot, osh, R);
             pz[q] = kw >> pk_shift;
           } else {
             d = L.dig[i];
@@ -1431,7 +1433,10 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
           uint32_t key = 0;
           if (i < n) {
             const uint32_t sp = owner_lut(s_lb, s_ot, osh, R, (int64_t)L.row[i]);
-            key = sp * R + (L.dig[i] >> sg.bits);
+            uint32_t di;
+            if constexpr (Lds::slim) di = digit_of(L.key[i] & pk_mask, sg, s_lb, s_ot, osh, R);
+            else di = L.dig[i];
+            key = sp * R + (di >> sg.bits);
           }
           wave_add_xfer(i < n, key, pz[q], (uint64_t*)it->xfer_cells, (uint64_t*)it->xfer_bytes);
         }
@@ -1481,13 +1486,15 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 // cells per lane in flight). It leaves a call whose records could not be
 // packed to the plain kernel launched beside it, which in turn leaves packed
 // calls to it (pk_split).
-template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false>
+template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false, bool kSlimParts = false>
 __global__ __launch_bounds__(kBlock, kSlim ? (kPass0 ? 768 / kBlock : 2048 / kBlock) : (kDefer ? 768 / kBlock : 2))
 void k_pass_scatter(PassArgs a) {
   static_assert(!kSlim || (kPass0 != kDefer && !kVal), "slim: a packed first or records-only pass");
-  // only the first pass may split by partition (not in its slim form)
-  constexpr int kFan = kPass0 ? (kSlim ? 1 << kMaxPassBits : kMaxFanout) : kFanBits;
-  constexpr bool kParts = kPass0 && !kSlim;
+  static_assert(!kSlimParts || (kSlim && kPass0), "partitions: the slim first pass");
+  // only the first pass may split by partition (its slim form up to a fan-out of 512)
+  constexpr int kFan = kPass0 ? (kSlim ? (kSlimParts ? 2 << kMaxPassBits : 1 << kMaxPassBits) : kMaxFanout)
+                              : kFanBits;
+  constexpr bool kParts = kPass0 && (!kSlim || kSlimParts);
   __shared__ SortLdsT<kFan, !kDefer, kSlim> L;
   __shared__ uint32_t s_rc[kFan];                       // running destination cell per digit (segment relative)
   __shared__ uint64_t s_rb[kDefer && !kSlim ? 1 : kFan];  // running destination byte per digit
@@ -1501,8 +1508,8 @@ void k_pass_scatter(PassArgs a) {
   if constexpr (kSlim) {
     if (packed_records(a.pk_on, a.no_pack)) {
       if constexpr (kPass0)
-        scatter_body<true, false, false, true, true>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
-                                                     s_extra, s_red);
+        scatter_body<true, false, false, true, true, decltype(L), kSlimParts>(
+            a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra, s_red);
       else
         scatter_body<false, true, false, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
                                                       s_extra, s_red);
@@ -2501,8 +2508,12 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
 }
 
 // The caller launches the plain first pass beside it with pk_split set.
+// slim0 == 2: some item splits by partition (fan-out at most 512).
 hipError_t launch_pass0_slim(const PassArgs& a, hipStream_t s) {
-  if (a.g8)
+  if (a.g8 && a.slim0 == 2)
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true, true>), grid1(a.g8),
+                       dim3(G::kBlock), 0, s, a);
+  else if (a.g8)
     hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true>), grid1(a.g8), dim3(G::kBlock),
                        0, s, a);
   return hipGetLastError();

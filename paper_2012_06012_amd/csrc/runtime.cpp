@@ -681,11 +681,13 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
   int32_t pk_keys = pk_on;
   for (uint32_t i = 0; i < n && pk_keys; ++i)
     if (items[i].d.flags & MGT_FIXED_WIDTH) pk_keys = 0;
-  // every item's first pass split by column bits (no partitions): the slim
-  // first pass takes packed records
-  bool bits0 = n >= 1;
-  for (uint32_t i = 0; i < n; ++i)
-    if (items[i].s.part_mode) bits0 = false;
+  // The slim first pass takes packed records: its bits-only form when every
+  // item's first pass splits by column bits, its partition form (fan-out up
+  // to 512) when some item's first pass splits by partition.
+  int32_t slim_form = n >= 1 ? 1 : 0;
+  for (uint32_t i = 0; i < n && slim_form; ++i)
+    if (items[i].s.part_mode)
+      slim_form = fanout(items[i].s, 0, items[i].d.n_parts) <= 512u ? 2 : 0;
   for (int l = 0; l < L; ++l) {
     PassArgs a{};
     a.items = d_items;
@@ -721,7 +723,7 @@ int run(mgt_plan_s* p, Items items, const Layout& y, void* ws, int32_t* d_status
     a.pk_on = pk_on;
     a.no_pack = d_no_pack;
     a.pk_keys = pk_keys;
-    a.slim0 = (l == 0 && !vc && bits0) ? 1 : 0;
+    a.slim0 = (l == 0 && !vc) ? slim_form : 0;
     a.rec12 = (l == L - 1) ? rec12 : 0;
     a.big_seg = d_big_seg;
     MGT_HIP(launch_pass_hist(a, s));

@@ -115,14 +115,14 @@ def profiler_kernel_name(stage: str, pass_idx: int, n_passes: int, partitioned: 
         return "mgt::geo256::k_finish<%s>" % ("true" if n_passes >= 2 else "false")
     if stage == "scatter":
         if pass_idx == 0:
-            if packed:
-                return "mgt::geo256::k_pass_scatter<true, false, false, true, %s>" % (
+            if packed:  # (the bench's variable-width matrices: the key-word form)
+                return "mgt::geo256::k_pass_scatter<true, false, false, true, %s, false>" % (
                     "true" if partitioned else "false")
-            return "mgt::geo256::k_pass_scatter<true, false, false, false, false>"
+            return "mgt::geo256::k_pass_scatter<true, false, false, false, false, false>"
         if pass_idx == n_passes - 1:  # records only; 512-thread form for single matrices
-            return "mgt::geo512::k_pass_scatter<false, true, false, %s, false>" % (
+            return "mgt::geo512::k_pass_scatter<false, true, false, %s, false, false>" % (
                 "true" if packed else "false")
-        return "mgt::geo256::k_pass_scatter<false, false, false, false, false>"
+        return "mgt::geo256::k_pass_scatter<false, false, false, false, false, false>"
     return stage
 
 

@@ -1322,10 +1322,10 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       else load_sub_rec(nxt, a.ks_in, a.rk_in, nullptr, sg.cell0 + c1, n1, tid);
     }
     if constexpr (Lds::slim) {  // packed records: the whole (column | size) word
-      static_assert(kPk && (kDefer || kPk4), "the slim LDS form is for packed records");
-      uint32_t kw[kItems];
+      static_assert(kPk, "the slim LDS form is for packed records");
+      uint32_t kw[kItems];  // (a first pass reading columns packs the word here)
 #pragma unroll
-      for (int r = 0; r < kItems; ++r) kw[r] = cur.a[r];
+      for (int r = 0; r < kItems; ++r) kw[r] = (kDefer || kPk4) ? cur.a[r] : key[r] | (sz[r] << pk_shift);
       sort_sub<false>(L, F, dbits, n, kw, dg, sz, row, idx, src, pk_shift);
     } else {
       sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
@@ -1486,11 +1486,12 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 // cells per lane in flight). It leaves a call whose records could not be
 // packed to the plain kernel launched beside it, which in turn leaves packed
 // calls to it (pk_split).
-template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false, bool kSlimParts = false>
+template <bool kPass0, bool kDefer, bool kVal, bool kSlim = false, bool kSlimParts = false,
+          bool kSlimCols = false>
 __global__ __launch_bounds__(kBlock, kSlim ? (kPass0 ? 768 / kBlock : 2048 / kBlock) : (kDefer ? 768 / kBlock : 2))
 void k_pass_scatter(PassArgs a) {
   static_assert(!kSlim || (kPass0 != kDefer && !kVal), "slim: a packed first or records-only pass");
-  static_assert(!kSlimParts || (kSlim && kPass0), "partitions: the slim first pass");
+  static_assert(!(kSlimParts || kSlimCols) || (kSlim && kPass0), "forms of the slim first pass");
   // only the first pass may split by partition (its slim form up to a fan-out of 512)
   constexpr int kFan = kPass0 ? (kSlim ? (kSlimParts ? 2 << kMaxPassBits : 1 << kMaxPassBits) : kMaxFanout)
                               : kFanBits;
@@ -1508,7 +1509,7 @@ void k_pass_scatter(PassArgs a) {
   if constexpr (kSlim) {
     if (packed_records(a.pk_on, a.no_pack)) {
       if constexpr (kPass0)
-        scatter_body<true, false, false, true, true, decltype(L), kSlimParts>(
+        scatter_body<true, false, false, true, !kSlimCols, decltype(L), kSlimParts>(
             a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si, s_extra, s_red);
       else
         scatter_body<false, true, false, true, false>(a, L, s_rc, s_rb, s_lb, s_ot, s_seg, s_si,
@@ -2488,7 +2489,7 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
   if (a.g8) {
     if (a.pass == 0 && a.has_val)
       hipLaunchKernelGGL((G::k_pass_scatter<true, false, true>), grid1(a.g8), dim3(G::kBlock), 0, s, a);
-    else if (a.pass == 0 && a.pk_on && a.pk_keys && a.slim0) {
+    else if (a.pass == 0 && a.pk_on && a.slim0) {
       // packed records in the slim 512-thread form; the plain kernel takes the rest
       PassArgs b = a;
       b.pk_split = 1;
@@ -2508,14 +2509,20 @@ hipError_t launch_pass_scatter(const PassArgs& a, hipStream_t s) {
 }
 
 // The caller launches the plain first pass beside it with pk_split set.
-// slim0 == 2: some item splits by partition (fan-out at most 512).
+// slim0 == 2: some item splits by partition (fan-out at most 512). Without
+// the first histogram's key words (fixed-width items) the pass reads the
+// columns and packs the words itself.
 hipError_t launch_pass0_slim(const PassArgs& a, hipStream_t s) {
-  if (a.g8 && a.slim0 == 2)
-    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true, true>), grid1(a.g8),
-                       dim3(G::kBlock), 0, s, a);
-  else if (a.g8)
-    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true>), grid1(a.g8), dim3(G::kBlock),
-                       0, s, a);
+  if (!a.g8) return hipSuccess;
+  const dim3 g = grid1(a.g8), b(G::kBlock);
+  if (a.slim0 == 2 && a.pk_keys)
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true, true>), g, b, 0, s, a);
+  else if (a.slim0 == 2)
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true, true, true>), g, b, 0, s, a);
+  else if (a.pk_keys)
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true>), g, b, 0, s, a);
+  else
+    hipLaunchKernelGGL((G::k_pass_scatter<true, false, false, true, false, true>), g, b, 0, s, a);
   return hipGetLastError();
 }
 

@@ -1192,6 +1192,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
   const void* const i_rp = it->row_ptr;
   const uint64_t i_nrows = (uint64_t)it->n_rows;
   const uint8_t* const i_pay = it->payload;
+  const uint64_t i_pbytes = (uint64_t)it->payload_bytes;
   const int32_t i_fw = it->fixed_w;
   const int pk_shift = it->pk_shift;  // packed records: column bits
   const uint32_t pk_mask = (uint32_t)((1ull << pk_shift) - 1u);
@@ -1310,6 +1311,35 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
       if constexpr (kBitsOnly) dg[r] = i < n ? digit_bits(key[r], sg) : 0u;
       else dg[r] = i < n ? digit_of(key[r], sg, s_lb, s_ot, osh, R) : 0u;
     }
+    // Slim first pass split by column bits: a wave's cells are consecutive
+    // input cells, so their payloads form one byte range of the input. One
+    // dword of each of its 128-byte lines (up to 128 lines, 16 KB) is read
+    // now, so that the payload gathers after the sort find the lines in the
+    // caches instead of waiting on HBM. Each dword read lies in an aligned
+    // line holding at least one byte of the range (the same page). The
+    // values are consumed after the sort, where the wait is free.
+    uint32_t touch[2] = {0u, 0u};
+    if constexpr (kPass0 && kBitsOnly) {
+      uint32_t whi = 0;  // end of the wave's range, relative to the sub-chunk
+#pragma unroll
+      for (int r = 0; r < kItems; ++r) {
+        const uint32_t i = w * kWaveCells + r * kWave + lane;
+        if (i < n) whi = max(whi, src[r] + sz[r]);
+      }
+#pragma unroll
+      for (int o = kWave / 2; o >= 1; o >>= 1) whi = max(whi, (uint32_t)__shfl_xor((int)whi, o, kWave));
+      const uint64_t b0 = sub_base + (uint32_t)__builtin_amdgcn_readfirstlane((int)src[0]);
+      const uint64_t b1 = min(sub_base + whi, i_pbytes);
+      if (w * kWaveCells < n && b0 < b1) {  // wave-uniform
+        const uintptr_t p0 = (uintptr_t)(i_pay + b0) & ~(uintptr_t)127;
+        const uintptr_t pe = (uintptr_t)(i_pay + b1);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uintptr_t q = p0 + ((uintptr_t)(k * kWave + lane) << 7);
+          if (q < pe) touch[k] = *(const GMEM uint32_t*)q;
+        }
+      }
+    }
     // The next sub-chunk's loads go out once this one's registers have been
     // read (the wait counter is in order, so a use of the current loads after
     // issuing these would wait for these too) and fly during the sort.
@@ -1327,6 +1357,7 @@ __device__ __forceinline__ void scatter_body(const PassArgs& a, Lds& L, uint32_t
 #pragma unroll
       for (int r = 0; r < kItems; ++r) kw[r] = (kDefer || kPk4) ? cur.a[r] : key[r] | (sz[r] << pk_shift);
       sort_sub<false>(L, F, dbits, n, kw, dg, sz, row, idx, src, pk_shift);
+      if constexpr (kPass0 && kBitsOnly) asm volatile("" ::"v"(touch[0]), "v"(touch[1]));
     } else {
       sort_sub<!kPk>(L, F, dbits, n, key, dg, sz, row, idx, src);
     }

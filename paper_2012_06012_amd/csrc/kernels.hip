@@ -1945,18 +1945,21 @@ __global__ __launch_bounds__(kBlock, 2) void k_finish(FinishArgs a) {
 // more) is marked 0 in bucket_done and left to k_finish, which skips those
 // marked 1. A bucket of 2^7 columns of the large multigraph holds 8,192 cells
 // on average and at most 8,834, under kBkCap.
-constexpr int kBkItems = 9;  // cells per lane
-constexpr int kBkPay = 2;    // cells per lane whose payload is in flight
+constexpr int kBkPay = 2;  // cells per lane whose payload is in flight
 
-// Two geometries: 1,024 threads (one workgroup per CU, buckets of up to 9,216
-// cells) and 512 threads (two workgroups per CU, up to 4,608 cells). With two
-// per CU, one workgroup's loads and LDS sort run while the other gathers, so
-// the CU keeps L2 misses in flight through every phase.
+// Two geometries: 1,024 threads (one workgroup per CU, ten cells per lane:
+// buckets of up to 10,240 cells, 156 KB of LDS) and 512 threads (two
+// workgroups per CU, nine cells per lane: up to 4,608 cells, 80 KB each).
+// With two per CU, one workgroup's loads and LDS sort run while the other
+// gathers, so the CU keeps L2 misses in flight through every phase. A tenth
+// cell per lane would slow the 512-thread form, whose buckets stay under
+// 4,608 cells anyway when it is chosen.
 template <int kBkBlock>
 struct BkGeo {
   static constexpr int kNW = kBkBlock / kWave;
-  static constexpr int kCap = kBkBlock * kBkItems;     // cells of a bucket held at once
-  static constexpr int kWaveCells = kBkItems * kWave;  // contiguous cells of one wave
+  static constexpr int kItems = kBkBlock >= 1024 ? 10 : 9;  // cells per lane
+  static constexpr int kCap = kBkBlock * kItems;            // cells of a bucket held at once
+  static constexpr int kWaveCells = kItems * kWave;         // contiguous cells of one wave
 };
 
 template <int kBkBlock>
@@ -2003,6 +2006,7 @@ __device__ __forceinline__ bool bucket_loadable(const Seg& s) {
 // [w * kBkWaveCells, (w + 1) * kBkWaveCells) (clamped into the bucket), each
 // as (column | size, row, payload offset low and high words). rec12: the
 // records are 12 bytes, the offset stored relative to the bucket's first byte.
+template <int kBkItems>
 __device__ __forceinline__ void load_bucket(v4u (&r)[kBkItems], const uint32_t* rso, const Seg& s,
                                             uint32_t tid, bool rec12) {
   constexpr int kBkWaveCells = kBkItems * kWave;
@@ -2024,6 +2028,7 @@ __device__ __forceinline__ void load_bucket(v4u (&r)[kBkItems], const uint32_t* 
   }
 }
 
+template <int kBkItems>
 __device__ __forceinline__ void zero_bucket(v4u (&r)[kBkItems]) {
 #pragma unroll
   for (int q = 0; q < kBkItems; ++q) r[q] = v4u{0u, 0u, 0u, 0u};
@@ -2032,6 +2037,7 @@ __device__ __forceinline__ void zero_bucket(v4u (&r)[kBkItems]) {
 template <int kBkBlock>
 __global__ __launch_bounds__(kBkBlock, 4) void k_finish_bucket(FinishArgs a) {
   constexpr int kBkNW = BkGeo<kBkBlock>::kNW;
+  constexpr int kBkItems = BkGeo<kBkBlock>::kItems;
   constexpr int kBkCap = BkGeo<kBkBlock>::kCap;
   constexpr int kBkWaveCells = BkGeo<kBkBlock>::kWaveCells;
   __shared__ BucketLds<kBkBlock> L;

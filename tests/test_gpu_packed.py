@@ -207,7 +207,7 @@ def test_hot_columns_packed(monkeypatch):
 @pytest.mark.parametrize("threads", [None, "512", "1024"])
 def test_whole_bucket_forms(threads, monkeypatch):
     # packed buckets of every size class in one call: up to 4,608 cells (the
-    # 512-thread whole-bucket finish, two workgroups per CU), up to 9,216 (the
+    # 512-thread whole-bucket finish, two workgroups per CU), up to 10,240 (the
     # 1,024-thread form, which runs after it and takes what it left) and more
     # (k_finish). Unset: both forms in turn; "512" or "1024": that form alone.
     if threads is not None:
@@ -220,11 +220,13 @@ def test_whole_bucket_forms(threads, monkeypatch):
     nnz = int(rp[-1])
     col = rng.integers(0, n_cols, size=nnz).astype(np.int32)
     hot = rng.random(nnz)
-    col[hot < 0.06] = 1234                    # a bucket of 4,608 to 9,216 cells
-    col[(hot >= 0.06) & (hot < 0.17)] = 50000  # a bucket of more than 9,216
+    col[hot < 0.06] = 1234                    # a bucket of 4,608 to 10,240 cells
+    col[(hot >= 0.06) & (hot < 0.17)] = 50000  # a bucket of more than 10,240
+    col[(hot >= 0.17) & (hot < 0.25)] = 20000  # one of 9,216 to 10,240 (1,024 threads only)
     for i in range(n_rows):
         col[rp[i]:rp[i + 1]].sort()
-    assert 4608 < (col == 1234).sum() <= 9216 - 200 and (col == 50000).sum() > 9216
+    assert 4608 < (col == 1234).sum() <= 9216 - 200 and (col == 50000).sum() > 10240
+    assert 9216 < (col == 20000).sum() <= 10240 - 400
     a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz) * 4,
                     fill_seed=7)
     _check(a, False, 0, monkeypatch)
@@ -254,7 +256,7 @@ def test_twelve_byte_records_all_finish_forms(threads, monkeypatch):
     # a single matrix whose tiles hold 4,096 cells or more: its records-only
     # pass runs in the slim form and writes 12-byte records (payload offset
     # relative to the finish bucket's first byte), read back by every finish
-    # path: buckets of up to 4,608 cells, up to 9,216, and more (k_finish)
+    # path: buckets of up to 4,608 cells, up to 10,240, and more (k_finish)
     if threads is not None:
         monkeypatch.setenv("MGT_BUCKET_THREADS", threads)
     rng = np.random.default_rng(47)
@@ -269,7 +271,7 @@ def test_twelve_byte_records_all_finish_forms(threads, monkeypatch):
     col[(hot >= 0.0017) & (hot < 0.0047)] = 50000
     for i in range(n_rows):
         col[rp[i]:rp[i + 1]].sort()
-    assert 4608 < (col == 1234).sum() <= 9000 and (col == 50000).sum() > 9216
+    assert 4608 < (col == 1234).sum() <= 9000 and (col == 50000).sum() > 10240
     a = from_arrays(n_rows, n_cols, rp, col, widths=rng.integers(0, 13, size=nnz) * 4,
                     fill_seed=9)
     from paper_2012_06012_amd import mgt
